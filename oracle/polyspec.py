@@ -1,0 +1,380 @@
+"""Plain FP64 implementation of the Scoccimarro-type FFT polyspectrum estimator.
+
+TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the benchmark's
+CPU-baseline leg; never by the library.  Written from Tomlinson, Jeong & Kim
+(2019), "Efficient parallel algorithm for estimating higher-order polyspectra":
+
+* Sec. 2, the direct estimator (label eq:estimateBk) averages the product of the
+  density at n wave vectors, one per shell, over every closed configuration.
+* Sec. 2, the Fourier form of the Dirac delta turns that sum into the grid sum of
+  a product of shell-filtered inverse transforms I_k(x) (labels eq:Bkfast and
+  eq:estimator); the same sum on a unit field gives the polygon volume
+  (labels eq:volume, eq:Vn).
+* Appendix A writes the estimator with unnormalised DFTs (FFTW convention):
+  B = (V_f^{n-1}/V_n) (V^{n-1}/N^{3n}) N^-3 sum_x prod_j FFTW(I~_{k_j}), and the
+  polygon count as N^-3 sum_x prod_j FFTW(iota~_{k_j}) over unit shells.
+
+Readings taken where the paper is loose (each is also listed in the design
+notes of the repository):
+
+* Shell s (s = 1..N_b) of width D holds the modes with (s - 1/2) D <= |q| < (s + 1/2) D,
+  |q| in units of k_f.  The paper writes |q - k_i| < dk/2 with strict bounds; the
+  half-open interval puts every mode with D/2 <= |q| < (N_b + 1/2) D in exactly one
+  shell.  The DC mode is never binned.  Membership is decided exactly, in integers.
+* delta_hat is the unnormalised forward DFT (e^{-i}) of the real grid field;
+  shell fields use the unnormalised inverse (e^{+i}).  The sign of the exponent
+  does not change a grid sum of real products.
+* The polygon count is n_t = N^-3 sum_x prod_j c_{t_j}[x] (no extra V_f factor),
+  which is exactly the number of ordered closed vector n-tuples with q_j in
+  shell t_j (closure taken modulo N on the periodic grid).
+* Output tuples are sorted t_1 <= ... <= t_n, lexicographic with t_n fastest,
+  restricted to those with n_t > 0.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+try:
+    import scipy.fft as _sfft
+
+    def _workers():
+        try:
+            return max(1, len(os.sched_getaffinity(0)))
+        except Exception:  # pragma: no cover
+            return os.cpu_count() or 1
+
+    def rfftn(a):
+        return _sfft.rfftn(a, workers=_workers())
+
+    def irfftn(a, s):
+        return _sfft.irfftn(a, s=s, workers=_workers())
+
+    def irfft2(a, s):
+        return _sfft.irfft2(a, s=s, workers=_workers())
+except Exception:  # pragma: no cover
+    rfftn = np.fft.rfftn
+
+    def irfftn(a, s):
+        return np.fft.irfftn(a, s=s)
+
+    def irfft2(a, s):
+        return np.fft.irfft2(a, s=s)
+
+__all__ = [
+    "shell_thresholds", "shell_of_squared_norm", "squared_norm_grid", "shell_id_grid",
+    "outer_radius", "is_alias_free", "sorted_tuples", "candidate_tuples", "pair_list",
+    "shell_mode_counts", "shell_fields", "shell_fields_from_hat", "count_fields",
+    "shell_fields_on_planes", "product_sums", "counts_from_sums", "polygon_counts",
+    "polyspectrum", "adjoint_weights", "gradient", "physical_factor",
+]
+
+
+# ----------------------------------------------------------------------------
+# Binning (Sec. 2: a mode belongs to the bin of k_i when |q - k_i| < dk/2;
+# Appendix A: the unit shell iota~ is 1 inside that shell and 0 elsewhere).
+# ----------------------------------------------------------------------------
+def shell_thresholds(n_shells: int, width: float) -> list[int]:
+    """T_1..T_{N_b+1}: T_s is the smallest integer Q = |q|^2 with 4Q >= ((2s-1) D)^2.
+
+    Shell s holds the integer squared norms T_s <= Q < T_{s+1}.  D is taken as the
+    exact rational value of the float passed in, so the compare is exact.
+    """
+    D = Fraction(width)
+    out = []
+    for s in range(1, n_shells + 2):
+        edge2 = ((2 * s - 1) * D) ** 2          # (2 |q|_edge)^2 = 4 Q_edge
+        out.append(math.ceil(edge2 / 4))
+    return out
+
+
+def shell_of_squared_norm(Q: np.ndarray, n_shells: int, width: float) -> np.ndarray:
+    """Shell index (1..N_b) of integer squared norms Q, 0 when Q lies in no shell."""
+    T = np.asarray(shell_thresholds(n_shells, width), dtype=np.int64)
+    Q = np.asarray(Q, dtype=np.int64)
+    s = np.searchsorted(T, Q, side="right")     # number of thresholds <= Q
+    s = np.where((s >= 1) & (s <= n_shells), s, 0)
+    return s.astype(np.int64)
+
+
+def squared_norm_grid(N: int, half: bool = True) -> np.ndarray:
+    """Integer |q|^2 on the rfftn layout [N, N, N//2+1] (or the full [N, N, N])."""
+    k = np.fft.fftfreq(N, d=1.0 / N).round().astype(np.int64)   # 0..N/2-1, -N/2..-1
+    kz = np.arange(N // 2 + 1, dtype=np.int64) if half else k
+    return k[:, None, None] ** 2 + k[None, :, None] ** 2 + kz[None, None, :] ** 2
+
+
+def shell_id_grid(N: int, n_shells: int, width: float, half: bool = True) -> np.ndarray:
+    return shell_of_squared_norm(squared_norm_grid(N, half), n_shells, width)
+
+
+def outer_radius(n_shells: int, width: float) -> float:
+    """K_e = (N_b + 1/2) D, the outer edge of the last shell in units of k_f."""
+    return (n_shells + 0.5) * width
+
+
+def is_alias_free(N: int, order: int, n_shells: int, width: float) -> bool:
+    """n K_e <= N: no sum of n shell vectors can wrap around the periodic grid.
+
+    Sec. 1 and Sec. 4.2 require a grid of at least (n N_max)^3 for the n-point
+    function; with the outer edge K_e the exact condition is n K_e <= N.
+    """
+    return order * Fraction(width) * Fraction(2 * n_shells + 1, 2) <= N
+
+
+def shell_mode_counts(N: int, n_shells: int, width: float) -> np.ndarray:
+    """|S_s| for s = 1..N_b, counted over the full periodic grid."""
+    sid = shell_id_grid(N, n_shells, width, half=False)
+    return np.bincount(sid.ravel(), minlength=n_shells + 1)[1:]
+
+
+# ----------------------------------------------------------------------------
+# Tuples (Sec. 4.3: k_1 >= ... >= k_n, flattened row-major with k_n fastest;
+# stored here in the equivalent ascending form t_1 <= ... <= t_n).
+# ----------------------------------------------------------------------------
+def sorted_tuples(order: int, n_shells: int) -> np.ndarray:
+    """All t_1 <= ... <= t_n over shells 1..N_b, lexicographic, t_n fastest."""
+    tl = list(itertools.combinations_with_replacement(range(1, n_shells + 1), order))
+    return np.asarray(tl, dtype=np.int64).reshape(-1, order)
+
+
+def candidate_tuples(order: int, n_shells: int, alias_free: bool = True) -> np.ndarray:
+    """Sorted tuples that can close: t_n < t_1 + ... + t_{n-1} + n/2 when alias-free.
+
+    |q_n| = |q_1 + ... + q_{n-1}| <= sum |q_j| < sum (t_j + 1/2) D, while q_n in
+    shell t_n needs |q_n| >= (t_n - 1/2) D.  With wrap-around (aliasing) any
+    sorted tuple can close modulo N, so every one is a candidate.
+    """
+    t = sorted_tuples(order, n_shells)
+    if not alias_free:
+        return t
+    lhs = 2 * t[:, -1]
+    rhs = 2 * t[:, :-1].sum(axis=1) + order
+    return t[lhs < rhs]
+
+
+def pair_list(n_shells: int) -> np.ndarray:
+    """Pairs (i, j), 1 <= i <= j <= N_b, lexicographic."""
+    return sorted_tuples(2, n_shells)
+
+
+# ----------------------------------------------------------------------------
+# Shell fields (Sec. 2, I_k(x) as the inverse transform of the shell-filtered
+# density; Appendix A: I[x] = (2 pi)^3 / N^3 FFTW(I~[q]); the prefactor is
+# pulled out, so the fields here are the raw unnormalised FFTW outputs).
+# ----------------------------------------------------------------------------
+def shell_fields_from_hat(delta_hat: np.ndarray, N: int, n_shells: int, width: float,
+                          shells=None) -> np.ndarray:
+    """d_s[x] = sum_q [s(q) = s] delta_hat[q] e^{+2 pi i q.x/N} for the requested shells."""
+    sid = shell_id_grid(N, n_shells, width)
+    shells = range(1, n_shells + 1) if shells is None else shells
+    out = np.empty((len(shells), N, N, N), dtype=np.float64)
+    for n, s in enumerate(shells):
+        masked = np.where(sid == s, delta_hat, 0.0)
+        out[n] = irfftn(masked, s=(N, N, N)) * float(N) ** 3
+    return out
+
+
+def shell_fields(delta: np.ndarray, n_shells: int, width: float, shells=None) -> np.ndarray:
+    """Shell fields of a real field delta[x] (float64 [N, N, N])."""
+    delta = np.asarray(delta, dtype=np.float64)
+    N = delta.shape[0]
+    return shell_fields_from_hat(rfftn(delta), N, n_shells, width, shells)
+
+
+def count_fields(N: int, n_shells: int, width: float, shells=None) -> np.ndarray:
+    """c_s[x]: the same transform of the unit shell iota~_s (Appendix A)."""
+    sid = shell_id_grid(N, n_shells, width)
+    shells = range(1, n_shells + 1) if shells is None else shells
+    out = np.empty((len(shells), N, N, N), dtype=np.float64)
+    for n, s in enumerate(shells):
+        out[n] = irfftn((sid == s).astype(np.float64), s=(N, N, N)) * float(N) ** 3
+    return out
+
+
+def shell_fields_on_planes(delta_hat: np.ndarray, N: int, n_shells: int, width: float,
+                           planes, shells=None, unit: bool = False) -> np.ndarray:
+    """Shell fields restricted to the x0-planes listed (for grids too large to hold whole).
+
+    The inverse transform along the first axis is evaluated only at the requested
+    x0 as an explicit sum, then each plane is the 2-D inverse real transform of the
+    remaining (q1, q2) half spectrum.  With unit=True the unit shells are used.
+    """
+    sid = shell_id_grid(N, n_shells, width)
+    planes = np.asarray(planes, dtype=np.int64)
+    shells = range(1, n_shells + 1) if shells is None else shells
+    q0 = np.fft.fftfreq(N, d=1.0 / N).round().astype(np.int64)
+    phase = np.exp(2j * np.pi * np.outer(planes, q0) / N)          # [P, N]
+    out = np.empty((len(shells), len(planes), N, N), dtype=np.float64)
+    for n, s in enumerate(shells):
+        if unit:
+            masked = (sid == s).astype(np.complex128)
+        else:
+            masked = np.where(sid == s, delta_hat, 0.0)
+        g = (phase @ masked.reshape(N, -1)).reshape(len(planes), N, N // 2 + 1)
+        out[n] = irfft2(g, s=(N, N)) * float(N) ** 2
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Product sums (Sec. 2: "the matrix inner product" of the shell fields;
+# Appendix A: sum over [x] of prod_j FFTW(I~_{k_j})).
+# ----------------------------------------------------------------------------
+def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192) -> np.ndarray:
+    """S_t = sum_x prod_j fields[t_j - 1][x] in FP64, for orders 2, 3 and 4.
+
+    The grid is summed in chunks; pair products d_i d_j are formed once per chunk
+    and multiplied against the remaining factor(s) with a matrix product.
+    """
+    tuples = np.asarray(tuples, dtype=np.int64)
+    order = tuples.shape[1]
+    nb = fields.shape[0]
+    flat = fields.reshape(nb, -1)
+    G = flat.shape[1]
+    pairs = pair_list(nb)
+    pidx = {(int(i), int(j)): n for n, (i, j) in enumerate(pairs)}
+    if order == 2:
+        acc = np.zeros((nb, nb))
+    elif order == 3:
+        acc = np.zeros((len(pairs), nb))
+    elif order == 4:
+        acc = np.zeros((len(pairs), len(pairs)))
+    else:
+        raise ValueError("product_sums supports orders 2, 3 and 4")
+    pi = pairs[:, 0] - 1
+    pj = pairs[:, 1] - 1
+    for x0 in range(0, G, chunk):
+        blk = flat[:, x0:x0 + chunk]
+        if order == 2:
+            acc += blk @ blk.T
+            continue
+        P = blk[pi] * blk[pj]
+        if order == 3:
+            acc += P @ blk.T
+        else:
+            acc += P @ P.T
+    if order == 2:
+        return acc[tuples[:, 0] - 1, tuples[:, 1] - 1]
+    if order == 3:
+        rows = np.array([pidx[(int(a), int(b))] for a, b in tuples[:, :2]], dtype=np.int64)
+        return acc[rows, tuples[:, 2] - 1]
+    rows = np.array([pidx[(int(a), int(b))] for a, b in tuples[:, :2]], dtype=np.int64)
+    cols = np.array([pidx[(int(a), int(b))] for a, b in tuples[:, 2:]], dtype=np.int64)
+    return acc[rows, cols]
+
+
+def counts_from_sums(C: np.ndarray, N: int, tol: float = 1e-3) -> np.ndarray:
+    """n_t = rint(C_t / N^3); the quotient must be an integer to within tol."""
+    q = np.asarray(C, dtype=np.float64) / float(N) ** 3
+    n = np.rint(q)
+    bad = np.abs(q - n) >= tol
+    if bad.any():
+        raise ArithmeticError(f"polygon count not integral: worst {np.abs(q - n).max():.3e}")
+    return n.astype(np.int64)
+
+
+def polygon_counts(N: int, order: int, n_shells: int, width: float, tuples) -> np.ndarray:
+    """Number of closed ordered vector n-tuples per tuple (Appendix A, count on a unit grid)."""
+    c = count_fields(N, n_shells, width)
+    return counts_from_sums(product_sums(c, tuples), N)
+
+
+def physical_factor(order: int, N: int, box_length: float) -> float:
+    """V^{n-1} / N^{3n} with V = L^3 (Appendix A); 1 when no box length is given."""
+    if not box_length:
+        return 1.0
+    V = float(box_length) ** 3
+    return V ** (order - 1) / float(N) ** (3 * order)
+
+
+def polyspectrum(delta: np.ndarray, order: int, n_shells: int, width: float,
+                 box_length: float = 0.0, allow_aliasing: bool = False,
+                 counts=None, return_fields: bool = False) -> dict:
+    """The estimator for one real field delta[x] (float64 [N, N, N]).
+
+    Returns the closing tuples, their counts n_t, the raw sums S_t and
+    B_t = physical_factor * S_t / (N^3 n_t).
+    """
+    delta = np.asarray(delta, dtype=np.float64)
+    N = delta.shape[0]
+    if 2 * outer_radius(n_shells, width) > N:
+        raise ValueError("outer shell edge beyond the Nyquist wavenumber")
+    alias_free = is_alias_free(N, order, n_shells, width)
+    if not alias_free and not allow_aliasing:
+        raise ValueError("configuration aliases: order * (N_b + 1/2) * width > N")
+    cand = candidate_tuples(order, n_shells, alias_free)
+    if counts is None:
+        n_cand = polygon_counts(N, order, n_shells, width, cand)
+    else:
+        n_cand = np.asarray(counts, dtype=np.int64)
+    keep = n_cand > 0
+    tuples = cand[keep]
+    n_t = n_cand[keep]
+    d = shell_fields(delta, n_shells, width)
+    S = product_sums(d, tuples)
+    B = physical_factor(order, N, box_length) * S / (float(N) ** 3 * n_t)
+    out = dict(tuples=tuples, counts=n_t, sums=S, B=B, candidates=cand, candidate_counts=n_cand)
+    if return_fields:
+        out["fields"] = d
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Gradient.  Not in the paper: the adjoint of the estimator, derived here.
+# B_t = c_t S_t with c_t = phys / (N^3 n_t) and S_t = sum_x prod_j d_{t_j}[x].
+# dS_t / d d_m[x] = sum over positions p with t_p = m of prod_{q != p} d_{t_q}[x].
+# Each d_m = C2R(M_m R2C(delta)) with an even real kernel, so its adjoint is the
+# same operator: dL/d delta = C2R( sum_m M_m R2C(a_m) ), a_m = dL/d d_m.
+# ----------------------------------------------------------------------------
+def adjoint_weights(tuples: np.ndarray, weights: np.ndarray, n_shells: int) -> np.ndarray:
+    """W[m, pair] for order 3: every position p of t adds w_t to W[t_p, t without p]."""
+    pairs = pair_list(n_shells)
+    pidx = {(int(i), int(j)): n for n, (i, j) in enumerate(pairs)}
+    W = np.zeros((n_shells, len(pairs)))
+    for t, w in zip(np.asarray(tuples), np.asarray(weights, dtype=np.float64)):
+        for p in range(3):
+            rest = tuple(sorted(int(v) for q, v in enumerate(t) if q != p))
+            W[int(t[p]) - 1, pidx[rest]] += w
+    return W
+
+
+def gradient(delta: np.ndarray, order: int, n_shells: int, width: float, grad_B: np.ndarray,
+             result: dict | None = None, box_length: float = 0.0,
+             allow_aliasing: bool = False, chunk: int = 8192) -> np.ndarray:
+    """dL/d delta[x] for L with dL/dB_t = grad_B[t] over the closing tuples (orders 2, 3)."""
+    delta = np.asarray(delta, dtype=np.float64)
+    N = delta.shape[0]
+    if result is None or "fields" not in result:
+        result = polyspectrum(delta, order, n_shells, width, box_length, allow_aliasing,
+                              return_fields=True)
+    tuples, n_t, d = result["tuples"], result["counts"], result["fields"]
+    w = np.asarray(grad_B, dtype=np.float64) * physical_factor(order, N, box_length) \
+        / (float(N) ** 3 * n_t)
+    flat = d.reshape(n_shells, -1)
+    a = np.zeros_like(flat)
+    if order == 2:
+        # S_(i,i) = sum d_i^2; only diagonal tuples close.
+        for t, wt in zip(tuples, w):
+            i, j = int(t[0]) - 1, int(t[1]) - 1
+            a[i] += wt * flat[j]
+            a[j] += wt * flat[i]
+    elif order == 3:
+        W = adjoint_weights(tuples, w, n_shells)
+        pairs = pair_list(n_shells)
+        pi, pj = pairs[:, 0] - 1, pairs[:, 1] - 1
+        for x0 in range(0, flat.shape[1], chunk):
+            blk = flat[:, x0:x0 + chunk]
+            a[:, x0:x0 + chunk] = W @ (blk[pi] * blk[pj])
+    else:
+        raise ValueError("gradient supports orders 2 and 3")
+    sid = shell_id_grid(N, n_shells, width)
+    g_hat = np.zeros((N, N, N // 2 + 1), dtype=np.complex128)
+    for m in range(n_shells):
+        am_hat = rfftn(a[m].reshape(N, N, N))
+        sel = sid == (m + 1)
+        g_hat[sel] += am_hat[sel]
+    return irfftn(g_hat, s=(N, N, N)) * float(N) ** 3

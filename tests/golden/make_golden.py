@@ -1,0 +1,32 @@
+"""Writes the stored expected values under tests/golden/ from the oracle alone.
+
+Run from the repository root: python tests/golden/make_golden.py
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+
+
+def main():
+    # |S_s| for unit-width shells s = 1..64 (full periodic grid large enough to hold them).
+    S = O.shell_mode_counts(132, 64, 1.0)
+    np.savetxt(os.path.join(HERE, "shell_modes_width1.txt"),
+               np.stack([np.arange(1, 65), S], axis=1), fmt="%d",
+               header="shell |S_s| for width 1 k_f, shell s = [(s-1/2), (s+1/2)) k_f")
+    # Triangle counts of the 64^3 grid with 16 unit-width shells.
+    cand = O.candidate_tuples(3, 16, True)
+    n = O.polygon_counts(64, 3, 16, 1.0, cand)
+    keep = n > 0
+    np.savetxt(os.path.join(HERE, "bispec_64_counts.txt"),
+               np.concatenate([cand[keep], n[keep, None]], axis=1), fmt="%d",
+               header="t1 t2 t3 n_t: closed ordered triangles, N=64, 16 shells of width 1 k_f")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+* exact lattice counts from the sum-of-three-squares theta series,
+* direct n-gon enumeration (the estimator's definition, Sec. 2),
+* the pair-sum rule for triangle counts,
+* the n = 2 reduction to the shell-averaged |delta_hat|^2 (Parseval),
+* the unit spectrum giving a unit polyspectrum (Sec. 4: counting by delta(k) = 1),
+* homogeneity, translation and lattice symmetry,
+* the paper's leading-order triangle counts (label eq:Ntri) as a loose sanity check,
+* the gradient against a closed form (n = 2) and central differences (n = 3).
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _r3_theta(qmax):
+    """r3(Q): number of integer (a, b, c) with a^2 + b^2 + c^2 = Q, as the coefficients of theta^3."""
+    theta = np.zeros(qmax + 1, dtype=np.int64)
+    k = 0
+    while k * k <= qmax:
+        theta[k * k] += 1 if k == 0 else 2
+        k += 1
+    t2 = np.convolve(theta, theta)[: qmax + 1]
+    return np.convolve(t2, theta)[: qmax + 1]
+
+
+@pytest.mark.parametrize("width", [1.0, 2.0, 1.5, 0.75])
+def test_shell_mode_counts_match_theta_series(width):
+    nb = 12
+    T = O.shell_thresholds(nb, width)
+    r3 = _r3_theta(T[-1])
+    expect = [int(r3[T[s]:T[s + 1]].sum()) for s in range(nb)]
+    N = 2 * int(np.ceil((nb + 0.5) * width)) + 2
+    assert list(O.shell_mode_counts(N, nb, width)) == expect
+
+
+def test_shell_edges_half_open():
+    # width 2: edges at odd radii; |q| = 3 (e.g. (2,2,1)) opens shell 2, |q| = 1 opens shell 1.
+    s = O.shell_of_squared_norm(np.array([0, 1, 8, 9, 24, 25, 120, 121]), 5, 2.0)
+    assert list(s) == [0, 1, 1, 2, 2, 3, 5, 0]
+    # width 1: |q|^2 = 2 (|q| = 1.414) in shell 1, 3 (1.732) in shell 2.
+    s = O.shell_of_squared_norm(np.array([0, 1, 2, 3, 6, 7]), 3, 1.0)
+    assert list(s) == [0, 1, 1, 2, 2, 3]
+
+
+def test_golden_shell_modes_width1():
+    got = O.shell_mode_counts(132, 64, 1.0)
+    ref = np.loadtxt(os.path.join(GOLDEN, "shell_modes_width1.txt"), dtype=np.int64)
+    assert np.array_equal(got, ref[:, 1])
+    T = O.shell_thresholds(64, 1.0)
+    r3 = _r3_theta(T[-1])
+    assert [int(r3[T[s]:T[s + 1]].sum()) for s in range(64)] == list(ref[:, 1])
+
+
+@pytest.mark.parametrize("order,nb,width", [(2, 7, 1.0), (3, 4, 1.0), (4, 3, 1.0),
+                                            (3, 3, 2.0), (3, 6, 1.0), (4, 4, 1.0)])
+def test_fft_estimator_equals_direct_enumeration(order, nb, width):
+    N = 16
+    delta = fieldgen.gaussian_field(N, 11 + order)
+    r = O.polyspectrum(delta, order, nb, width, allow_aliasing=True)
+    cnt, sums = O.bruteforce_polyspectrum(delta, order, nb, width, r["candidates"])
+    assert np.array_equal(cnt, r["candidate_counts"])
+    keep = cnt > 0
+    scale = np.abs(sums).max()
+    assert np.abs(sums.imag).max() <= 1e-12 * scale
+    np.testing.assert_allclose(sums[keep].real * N ** 3, r["sums"],
+                               rtol=0, atol=1e-12 * scale * N ** 3)
+    np.testing.assert_allclose(sums[keep].real / cnt[keep], r["B"], rtol=1e-10,
+                               atol=1e-12 * np.abs(r["B"]).max())
+
+
+def test_aliased_flag_required():
+    with pytest.raises(ValueError):
+        O.polyspectrum(np.zeros((16, 16, 16)), 3, 6, 1.0)
+
+
+def test_candidates_cover_every_closing_tuple():
+    N, nb = 16, 4
+    allt = O.sorted_tuples(3, nb)
+    cnt, _ = O.bruteforce_polyspectrum(np.ones((N, N, N)), 3, nb, 1.0, allt)
+    cand = {tuple(t) for t in O.candidate_tuples(3, nb, True).tolist()}
+    assert {tuple(t) for t, c in zip(allt.tolist(), cnt) if c > 0} <= cand
+
+
+def _counts_table(N, order, nb, width):
+    cand = O.candidate_tuples(order, nb, O.is_alias_free(N, order, nb, width))
+    n = O.polygon_counts(N, order, nb, width, cand)
+    return {tuple(t): int(c) for t, c in zip(cand.tolist(), n)}
+
+
+@pytest.mark.parametrize("N,nb,width", [(64, 16, 1.0), (48, 7, 2.0)])
+def test_pair_sum_rule(N, nb, width):
+    """sum_k n(i, j, k) = |S_i||S_j| - [i = j] |S_i| whenever q_1 + q_2 always lands in a shell."""
+    table = _counts_table(N, 3, nb, width)
+    S = O.shell_mode_counts(N, nb, width)
+    checked = 0
+    for i in range(1, nb + 1):
+        for j in range(i, nb + 1):
+            if i + j + 1 > nb:
+                continue
+            tot = sum(table.get(tuple(sorted((i, j, k))), 0) for k in range(1, nb + 1))
+            assert tot == S[i - 1] * S[j - 1] - (S[i - 1] if i == j else 0)
+            checked += 1
+    assert checked > 0
+
+
+def test_small_triangle_counts():
+    table = _counts_table(64, 3, 16, 1.0)
+    cnt, _ = O.bruteforce_polyspectrum(np.ones((16, 16, 16)), 3, 3, 1.0,
+                                       np.array([(1, 1, 1), (1, 1, 2), (1, 1, 3), (1, 2, 2),
+                                                 (1, 2, 3), (2, 2, 2), (2, 2, 3)]))
+    got = [table[t] for t in [(1, 1, 1), (1, 1, 2), (1, 1, 3), (1, 2, 2), (1, 2, 3),
+                              (2, 2, 2), (2, 2, 3)]]
+    assert got == list(cnt) == [120, 174, 12, 456, 414, 912, 944]
+
+
+def test_golden_bispec64_counts():
+    ref = np.loadtxt(os.path.join(GOLDEN, "bispec_64_counts.txt"), dtype=np.int64)
+    assert ref.shape == (564, 4)
+    S = O.shell_mode_counts(64, 16, 1.0)
+    table = {tuple(r[:3]): int(r[3]) for r in ref}
+    for i in range(1, 17):
+        for j in range(i, 17):
+            if i + j + 1 <= 16:
+                tot = sum(table.get(tuple(sorted((i, j, k))), 0) for k in range(1, 17))
+                assert tot == S[i - 1] * S[j - 1] - (S[i - 1] if i == j else 0)
+
+
+def test_power_spectrum_parseval():
+    N, nb = 32, 10
+    delta = fieldgen.gaussian_field(N, 5)
+    r = O.polyspectrum(delta, 2, nb, 1.0)
+    dhat = np.fft.fftn(delta)
+    sid = O.shell_id_grid(N, nb, 1.0, half=False)
+    ref = np.array([np.mean(np.abs(dhat[sid == s]) ** 2) for s in range(1, nb + 1)])
+    assert [tuple(t) for t in r["tuples"].tolist()] == [(s, s) for s in range(1, nb + 1)]
+    np.testing.assert_allclose(r["B"], ref, rtol=1e-11)
+    np.testing.assert_array_equal(r["counts"], O.shell_mode_counts(N, nb, 1.0))
+
+
+@pytest.mark.parametrize("order,nb", [(3, 8), (4, 5)])
+def test_unit_spectrum_gives_unit_polyspectrum(order, nb):
+    N = 32
+    r = O.polyspectrum(fieldgen.unit_spectrum_field(N), order, nb, 1.0)
+    np.testing.assert_allclose(r["B"], 1.0, rtol=1e-11)
+
+
+def test_homogeneity_and_symmetries():
+    N, nb = 32, 8
+    delta = fieldgen.lognormal_field(N, 7)
+    base = O.polyspectrum(delta, 3, nb, 1.0)
+    counts = base["candidate_counts"]
+    twice = O.polyspectrum(2.0 * delta, 3, nb, 1.0, counts=counts)
+    np.testing.assert_array_equal(twice["B"], 8.0 * base["B"])
+    scale = np.abs(base["B"]).max()
+    for moved in (np.roll(delta, (3, -5, 7), axis=(0, 1, 2)),
+                  np.transpose(delta, (2, 0, 1)),
+                  delta[::-1, :, :]):
+        r = O.polyspectrum(np.ascontiguousarray(moved), 3, nb, 1.0, counts=counts)
+        np.testing.assert_allclose(r["B"], base["B"], rtol=0, atol=1e-11 * scale)
+    # raw sums are symmetric in the tuple's order: compare (i, j, k) with its rotation
+    d = O.shell_fields(delta, nb, 1.0)
+    t = np.array([[1, 2, 3], [2, 2, 5]])
+    rot = np.array([[3, 1, 2], [5, 2, 2]])
+    s1 = [np.sum(d[a - 1] * d[b - 1] * d[c - 1]) for a, b, c in t]
+    s2 = [np.sum(d[a - 1] * d[b - 1] * d[c - 1]) for a, b, c in rot]
+    np.testing.assert_allclose(s1, O.product_sums(d, t), rtol=1e-12)
+    np.testing.assert_allclose(s2, s1, rtol=1e-12)
+
+
+def test_counts_near_leading_order_triangles():
+    """Eq. Ntri to within the paper's quoted ~20 % for open triangles at large k."""
+    table = _counts_table(64, 3, 16, 1.0)
+    rel = []
+    for (a, b, c), n in table.items():
+        if a >= 8 and c < a + b:      # open triangles (largest side c < a + b), away from large scales
+            rel.append(n / O.n_tri_leading(c, b, a, 1.0) - 1.0)
+    rel = np.abs(np.array(rel))
+    assert len(rel) > 20 and np.median(rel) < 0.2
+
+
+def test_gradient_power_spectrum_closed_form():
+    N, nb = 16, 5
+    delta = fieldgen.gaussian_field(N, 21)
+    r = O.polyspectrum(delta, 2, nb, 1.0, return_fields=True)
+    s = 3
+    g = np.zeros(len(r["tuples"]))
+    g[s - 1] = 1.0
+    grad = O.gradient(delta, 2, nb, 1.0, g, result=r)
+    np.testing.assert_allclose(grad, 2.0 * r["fields"][s - 1] / r["counts"][s - 1],
+                               rtol=0, atol=1e-12 * np.abs(grad).max())
+
+
+def test_gradient_bispectrum_central_differences():
+    N, nb = 16, 4
+    delta = fieldgen.gaussian_field(N, 31)
+    target = 0.5 * O.polyspectrum(fieldgen.gaussian_field(N, 32), 3, nb, 1.0)["B"]
+    r = O.polyspectrum(delta, 3, nb, 1.0, return_fields=True)
+    counts = r["candidate_counts"]
+    grad = O.gradient(delta, 3, nb, 1.0, 2.0 * (r["B"] - target), result=r)
+
+    def loss(dl):
+        return np.sum((O.polyspectrum(dl, 3, nb, 1.0, counts=counts)["B"] - target) ** 2)
+
+    rng = np.random.default_rng(3)
+    eps = 1e-3
+    for flat in rng.choice(N ** 3, size=6, replace=False):
+        idx = np.unravel_index(flat, (N, N, N))
+        dp = delta.copy(); dp[idx] += eps
+        dm = delta.copy(); dm[idx] -= eps
+        fd = (loss(dp) - loss(dm)) / (2 * eps)
+        assert abs(fd - grad[idx]) <= 1e-6 * np.abs(grad).max()
+
+
+def test_count_integrality_check_trips():
+    with pytest.raises(ArithmeticError):
+        O.counts_from_sums(np.array([64.0 ** 3 * 7.3]), 64)
+
+
+def test_slab_fields_match_full_fields():
+    N, nb = 32, 6
+    delta = fieldgen.gaussian_field(N, 8)
+    full = O.shell_fields(delta, nb, 1.0)
+    planes = [0, 5, 31]
+    part = O.shell_fields_on_planes(np.fft.rfftn(delta), N, nb, 1.0, planes)
+    np.testing.assert_allclose(part, full[:, planes], rtol=0, atol=1e-10 * np.abs(full).max())
+    cpart = O.shell_fields_on_planes(None, N, nb, 1.0, planes, unit=True)
+    cfull = O.count_fields(N, nb, 1.0)
+    np.testing.assert_allclose(cpart, cfull[:, planes], rtol=0, atol=1e-10 * np.abs(cfull).max())
