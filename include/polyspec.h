@@ -1,0 +1,154 @@
+/*
+ * polyspec.h -- C ABI of the MI355X (gfx950) polyspectrum estimator library.
+ *
+ * The library computes the angle-averaged n-point polyspectrum of a real field
+ * on a periodic N^3 grid with the FFT form of the estimator of Tomlinson, Jeong &
+ * Kim (2019) (Sec. 2: the Fourier representation of the Dirac delta turns the sum
+ * over closed n-gons into a grid sum of products of shell-filtered inverse
+ * transforms; Appendix A: unnormalised DFTs and the polygon-count normalisation
+ * obtained by running the same estimator on unit shells).
+ *
+ * Conventions shared by every call:
+ *  - delta_hat[q] is the unnormalised forward DFT (sum_x delta[x] e^{-2 pi i q.x/N});
+ *    shell fields d_s[x] = sum_q [s(q) = s] delta_hat[q] e^{+2 pi i q.x/N}.
+ *  - Shell s = 1..n_shells of width D (units of the fundamental wavenumber k_f)
+ *    holds the modes with (s - 1/2) D <= |q| < (s + 1/2) D, decided exactly on the
+ *    integer |q|^2.  The DC mode is in no shell.
+ *  - Tuples are sorted t_1 <= ... <= t_n, lexicographic with t_n fastest (the
+ *    paper's k_1 >= ... >= k_n row-major order, each tuple reversed).  Only tuples
+ *    that close (polygon count n_t > 0) are reported; n_closing is their number.
+ *  - B_t = f * S_t / (N^3 n_t) with S_t = sum_x prod_j d_{t_j}[x] and f = 1, or
+ *    f = V^{n-1} / N^{3n}, V = L^3, when box_length L > 0 (Appendix A).
+ *  - Every device pointer is caller-owned and must stay valid until the stream
+ *    work that uses it has finished.  Arrays are dense, row-major, last index
+ *    fastest.  Real fields are float32 [batch][N][N][N].
+ *  - Every call returns a status; none throws, aborts or exits.  A failed call
+ *    leaves the plan as it was, and polyspec_last_error() gives detail text.
+ *  - All work is enqueued on the plan's stream (a hipStream_t passed as void*,
+ *    NULL for the default stream) and is asynchronous unless stated otherwise.
+ *  - A plan is not thread-safe; use one plan per host thread.
+ */
+#ifndef POLYSPEC_H
+#define POLYSPEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct polyspec_plan_s* polyspec_plan_t;
+
+typedef enum {
+  POLYSPEC_OK = 0,
+  POLYSPEC_ERR_INVALID_ARG = 1,        /* bad descriptor field, null pointer, size mismatch */
+  POLYSPEC_ERR_ALIASING = 2,           /* order * (n_shells + 1/2) * width > N without ALLOW_ALIASING */
+  POLYSPEC_ERR_OUT_OF_MEMORY = 3,      /* device or host allocation failed */
+  POLYSPEC_ERR_DEVICE = 4,             /* a HIP runtime call or kernel launch failed */
+  POLYSPEC_ERR_COUNT_NOT_INTEGRAL = 5, /* a polygon count quotient was not within 1e-3 of an integer */
+  POLYSPEC_ERR_STATE = 6,              /* call out of order (contract before shells, ...) */
+  POLYSPEC_ERR_UNSUPPORTED = 7         /* valid request outside what this build implements */
+} polyspec_status;
+
+/* Arithmetic of the product-sum contraction.  Shell fields are always float32 and
+ * sums across grid tiles are always float64.  SPLIT_* carry each float32 operand as
+ * hi + lo of a 16-bit type and form hi*hi + hi*lo + lo*hi on the matrix cores,
+ * accumulating in float32.  SPLIT_FP16 scales every shell by a power of two so that
+ * its largest magnitude sits near 2^14; the scale is removed exactly in float64.
+ * (Not in the paper: a precision extension of its product-and-sum step.) */
+typedef enum {
+  POLYSPEC_FP32 = 0,
+  POLYSPEC_SPLIT_BF16 = 1,
+  POLYSPEC_SPLIT_FP16 = 2
+} polyspec_precision;
+
+enum {
+  POLYSPEC_INPUT_HALF_SPECTRUM = 1u, /* polyspec_shells input is delta_hat, complex64 [batch][N][N][N/2+1] */
+  POLYSPEC_ALLOW_ALIASING = 2u,      /* accept order*(n_shells+1/2)*width > N: exact mod-N estimator */
+  POLYSPEC_NAN_GUARD = 8u            /* contract reports POLYSPEC_ERR_DEVICE on a non-finite output */
+};
+
+typedef struct {
+  int32_t N;            /* grid points per side; a power of two, 32 <= N <= 1024            */
+  int32_t order;        /* n = 2, 3 or 4                                                     */
+  int32_t n_shells;     /* N_b >= 1; (N_b + 1/2) * width <= N/2; the matrix-core contraction
+                           handles N_b <= 64                                                 */
+  double shell_width;   /* D > 0, in units of k_f (exact binary value is used)              */
+  int32_t batch;        /* independent fields processed together, >= 1                      */
+  int32_t precision;    /* polyspec_precision                                                */
+  double box_length;    /* L; 0 => estimator units S/(N^3 n_t); > 0 => times V^{n-1}/N^{3n} */
+  uint32_t flags;       /* POLYSPEC_* flags above                                            */
+} polyspec_desc;
+
+/* Builds a plan for one geometry (Sec. 2 estimator; Appendix A counts).
+ * Validates the descriptor, builds the shell, tuple and tile tables, and computes
+ * the polygon counts n_t of every candidate tuple on the device in float64 (the
+ * estimator applied to unit shells, Sec. 4 and Appendix A).  Synchronises the
+ * stream once to read the counts back.  Returns POLYSPEC_ERR_COUNT_NOT_INTEGRAL if
+ * any count quotient misses an integer by 1e-3 or more.  *out receives the plan. */
+polyspec_status polyspec_plan(const polyspec_desc* desc, void* stream, polyspec_plan_t* out);
+
+/* Shell fields (Sec. 2, I_k(x); Appendix A, FFTW(I~)).  d_delta is a device
+ * pointer to float32 [batch][N][N][N] (or complex64 [batch][N][N][N/2+1] with
+ * POLYSPEC_INPUT_HALF_SPECTRUM).  Computes delta_hat on the ball of modes in any
+ * shell, then every d_s, and keeps them in the plan's workspace for contract and
+ * backward.  Asynchronous; d_delta may be reused once the stream has passed it. */
+polyspec_status polyspec_shells(polyspec_plan_t plan, const void* d_delta);
+
+/* Product sums and normalisation (Sec. 2, the grid sum of products of the I_k;
+ * Appendix A, division by N^3 and by the polygon count).  Writes B_t as float64
+ * [batch][n_closing] to d_out, and the raw sums S_t (float64, same shape) to
+ * d_raw_sums when it is not NULL.  POLYSPEC_ERR_STATE before polyspec_shells. */
+polyspec_status polyspec_contract(polyspec_plan_t plan, double* d_out, double* d_raw_sums);
+
+/* Adjoint of shells + contract (not in the paper): given dL/dB_t in d_grad_out
+ * (float64 [batch][n_closing]), writes dL/d delta to d_grad_delta as float32
+ * [batch][N][N][N], using the shell fields of the last polyspec_shells call.
+ * Order 3 only (POLYSPEC_ERR_UNSUPPORTED otherwise); real-space input only. */
+polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out, float* d_grad_delta);
+
+/* Bytes of device workspace the plan needs for shells, contract and backward. */
+polyspec_status polyspec_workspace_size(polyspec_plan_t plan, size_t* bytes);
+
+/* Hands the plan caller-owned device memory of at least polyspec_workspace_size()
+ * bytes (256-byte aligned).  Must precede the first polyspec_shells call; without
+ * it the plan allocates its own on first use and frees it in polyspec_destroy. */
+polyspec_status polyspec_set_workspace(polyspec_plan_t plan, void* d_ptr, size_t bytes);
+
+/* Switches the contraction arithmetic (polyspec_precision) for later calls. */
+polyspec_status polyspec_set_precision(polyspec_plan_t plan, int32_t precision);
+
+/* Host copies of the closing tuples and their counts.  *n_closing is always set;
+ * h_bins (int32 [n_closing][order]) and h_counts (int64 [n_closing]) are filled
+ * when not NULL.  Synchronous, touches no device memory. */
+polyspec_status polyspec_tuples(polyspec_plan_t plan, int64_t* n_closing, int32_t* h_bins,
+                                int64_t* h_counts);
+
+/* Every candidate tuple examined at plan time (sorted tuples that pass the
+ * triangle-type bound, or all sorted tuples when aliasing is allowed) with the
+ * float64 quotient C_t / N^3 whose rounding gave its count.  Same conventions
+ * as polyspec_tuples. */
+polyspec_status polyspec_candidates(polyspec_plan_t plan, int64_t* n_candidates, int32_t* h_bins,
+                                    double* h_quotients);
+
+/* Device pointer to the kept float32 shell fields [batch][n_shells][N][N][N]
+ * (owned by the plan, valid until the next polyspec_shells or polyspec_destroy),
+ * for inspection.  POLYSPEC_ERR_STATE before polyspec_shells. */
+polyspec_status polyspec_fields(polyspec_plan_t plan, const float** d_fields);
+
+/* Releases the plan and everything it allocated (not caller workspace).  Waits for
+ * the plan's stream.  NULL is accepted. */
+polyspec_status polyspec_destroy(polyspec_plan_t plan);
+
+const char* polyspec_status_string(polyspec_status st);
+
+/* Detail of the last failure on this plan (or of the last failed polyspec_plan when
+ * plan is NULL); valid until the next call on the same plan. */
+const char* polyspec_last_error(polyspec_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYSPEC_H */

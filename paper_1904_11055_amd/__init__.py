@@ -1,0 +1,280 @@
+"""MI355X (gfx950) angle-averaged polyspectrum estimator.
+
+Thin Python binding over ``libpolyspec.so`` (see ``include/polyspec.h``).  The
+functions named ``polyspec_*`` marshal arguments to the C calls of the same name;
+every step of the computation runs in the library's HIP kernels.  PyTorch is used
+only for device memory and the current stream.  ``Plan`` and ``polyspectrum``
+are conveniences on top (``polyspectrum`` is differentiable for order 3).
+
+The estimator is the FFT form of Tomlinson, Jeong & Kim (2019), Sec. 2 and
+Appendix A: B_t = sum_x prod_j d_{t_j}[x] / (N^3 n_t) over sorted shell tuples t,
+with d_s the unnormalised inverse transform of the density restricted to shell s
+and n_t the number of closed n-gons with sides in those shells.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "PolyspecError", "Plan", "polyspectrum", "load_library",
+    "FP32", "SPLIT_BF16", "SPLIT_FP16", "INPUT_HALF_SPECTRUM", "ALLOW_ALIASING", "NAN_GUARD",
+    "polyspec_plan", "polyspec_shells", "polyspec_contract", "polyspec_backward",
+    "polyspec_workspace_size", "polyspec_set_workspace", "polyspec_set_precision",
+    "polyspec_tuples", "polyspec_candidates", "polyspec_fields", "polyspec_destroy",
+    "polyspec_status_string", "polyspec_last_error",
+]
+
+FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2
+INPUT_HALF_SPECTRUM, ALLOW_ALIASING, NAN_GUARD = 1, 2, 8
+
+STATUS = {0: "POLYSPEC_OK", 1: "POLYSPEC_ERR_INVALID_ARG", 2: "POLYSPEC_ERR_ALIASING",
+          3: "POLYSPEC_ERR_OUT_OF_MEMORY", 4: "POLYSPEC_ERR_DEVICE",
+          5: "POLYSPEC_ERR_COUNT_NOT_INTEGRAL", 6: "POLYSPEC_ERR_STATE", 7: "POLYSPEC_ERR_UNSUPPORTED"}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpolyspec.so")
+
+
+class PolyspecError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+
+
+class polyspec_desc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("order", ctypes.c_int32), ("n_shells", ctypes.c_int32),
+                ("shell_width", ctypes.c_double), ("batch", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("box_length", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1904_11055_amd.build`")
+    try:  # bind to the HIP runtime torch already carries, when torch is present
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    lib = ctypes.CDLL(path)
+    P, V, D = ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER
+    sig = {
+        "polyspec_plan": (ctypes.c_int, [D(polyspec_desc), V, D(P)]),
+        "polyspec_shells": (ctypes.c_int, [P, V]),
+        "polyspec_contract": (ctypes.c_int, [P, V, V]),
+        "polyspec_backward": (ctypes.c_int, [P, V, V]),
+        "polyspec_workspace_size": (ctypes.c_int, [P, D(ctypes.c_size_t)]),
+        "polyspec_set_workspace": (ctypes.c_int, [P, V, ctypes.c_size_t]),
+        "polyspec_set_precision": (ctypes.c_int, [P, ctypes.c_int32]),
+        "polyspec_tuples": (ctypes.c_int, [P, D(ctypes.c_int64), V, V]),
+        "polyspec_candidates": (ctypes.c_int, [P, D(ctypes.c_int64), V, V]),
+        "polyspec_fields": (ctypes.c_int, [P, D(ctypes.c_void_p)]),
+        "polyspec_destroy": (ctypes.c_int, [P]),
+        "polyspec_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "polyspec_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str, plan=None):
+    if st != 0:
+        lib = load_library()
+        detail = lib.polyspec_last_error(plan).decode(errors="replace")
+        raise PolyspecError(st, where, detail)
+
+
+# --- same-name marshalling wrappers -------------------------------------------
+def polyspec_status_string(status: int) -> str:
+    return load_library().polyspec_status_string(status).decode()
+
+
+def polyspec_last_error(plan) -> str:
+    return load_library().polyspec_last_error(plan).decode(errors="replace")
+
+
+def polyspec_plan(N, order, n_shells, shell_width, batch=1, precision=FP32, box_length=0.0,
+                  flags=0, stream=None):
+    lib = load_library()
+    d = polyspec_desc(N, order, n_shells, float(shell_width), batch, precision, float(box_length), flags)
+    h = ctypes.c_void_p()
+    _check(lib.polyspec_plan(ctypes.byref(d), stream, ctypes.byref(h)), "polyspec_plan")
+    return h
+
+
+def polyspec_shells(plan, d_delta_ptr: int):
+    _check(load_library().polyspec_shells(plan, ctypes.c_void_p(d_delta_ptr)), "polyspec_shells", plan)
+
+
+def polyspec_contract(plan, d_out_ptr: int, d_raw_ptr: int | None = None):
+    _check(load_library().polyspec_contract(plan, ctypes.c_void_p(d_out_ptr),
+                                            ctypes.c_void_p(d_raw_ptr) if d_raw_ptr else None),
+           "polyspec_contract", plan)
+
+
+def polyspec_backward(plan, d_grad_out_ptr: int, d_grad_delta_ptr: int):
+    _check(load_library().polyspec_backward(plan, ctypes.c_void_p(d_grad_out_ptr),
+                                            ctypes.c_void_p(d_grad_delta_ptr)), "polyspec_backward", plan)
+
+
+def polyspec_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().polyspec_workspace_size(plan, ctypes.byref(n)), "polyspec_workspace_size", plan)
+    return n.value
+
+
+def polyspec_set_workspace(plan, d_ptr: int, nbytes: int):
+    _check(load_library().polyspec_set_workspace(plan, ctypes.c_void_p(d_ptr), nbytes),
+           "polyspec_set_workspace", plan)
+
+
+def polyspec_set_precision(plan, precision: int):
+    _check(load_library().polyspec_set_precision(plan, precision), "polyspec_set_precision", plan)
+
+
+def polyspec_tuples(plan, order: int):
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.polyspec_tuples(plan, ctypes.byref(n), None, None), "polyspec_tuples", plan)
+    bins = np.zeros((n.value, order), dtype=np.int32)
+    counts = np.zeros(n.value, dtype=np.int64)
+    _check(lib.polyspec_tuples(plan, ctypes.byref(n), bins.ctypes.data_as(ctypes.c_void_p),
+                               counts.ctypes.data_as(ctypes.c_void_p)), "polyspec_tuples", plan)
+    return bins, counts
+
+
+def polyspec_candidates(plan, order: int):
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.polyspec_candidates(plan, ctypes.byref(n), None, None), "polyspec_candidates", plan)
+    bins = np.zeros((n.value, order), dtype=np.int32)
+    quot = np.zeros(n.value, dtype=np.float64)
+    _check(lib.polyspec_candidates(plan, ctypes.byref(n), bins.ctypes.data_as(ctypes.c_void_p),
+                                   quot.ctypes.data_as(ctypes.c_void_p)), "polyspec_candidates", plan)
+    return bins, quot
+
+
+def polyspec_fields(plan) -> int:
+    ptr = ctypes.c_void_p()
+    _check(load_library().polyspec_fields(plan, ctypes.byref(ptr)), "polyspec_fields", plan)
+    return ptr.value
+
+
+def polyspec_destroy(plan):
+    _check(load_library().polyspec_destroy(plan), "polyspec_destroy")
+
+
+# --- conveniences ------------------------------------------------------------
+class Plan:
+    """One geometry (grid, order, shells) and batch, bound to torch's current stream."""
+
+    def __init__(self, N, order, n_shells, shell_width, batch=1, precision=FP32, box_length=0.0,
+                 flags=0, device=None):
+        import torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.N, self.order, self.n_shells, self.width = N, order, n_shells, float(shell_width)
+        self.batch, self.flags = batch, flags
+        self._precision = precision
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.handle = polyspec_plan(N, order, n_shells, shell_width, batch, precision, box_length,
+                                        flags, ctypes.c_void_p(self.stream.cuda_stream))
+        self.tuples, self.counts = polyspec_tuples(self.handle, order)
+        self.n_closing = len(self.counts)
+
+    @property
+    def precision(self):
+        return self._precision
+
+    @precision.setter
+    def precision(self, value):
+        polyspec_set_precision(self.handle, value)
+        self._precision = value
+
+    def candidates(self):
+        return polyspec_candidates(self.handle, self.order)
+
+    def shells(self, delta):
+        """delta: float32 [batch, N, N, N] (or complex64 half spectrum) on the plan's device."""
+        import torch
+        N = self.N
+        if self.flags & INPUT_HALF_SPECTRUM:
+            want, dt = (self.batch, N, N, N // 2 + 1), torch.complex64
+        else:
+            want, dt = (self.batch, N, N, N), torch.float32
+        if tuple(delta.shape) != want or delta.dtype != dt or delta.device != self.device:
+            raise ValueError(f"expected {dt} {want} on {self.device}, got {delta.dtype} {tuple(delta.shape)} "
+                             f"on {delta.device}")
+        delta = delta.contiguous()
+        polyspec_shells(self.handle, delta.data_ptr())
+        self._last_input = delta  # keep alive until the stream has consumed it
+
+    def contract(self, raw=False):
+        import torch
+        out = torch.empty((self.batch, self.n_closing), dtype=torch.float64, device=self.device)
+        rs = torch.empty_like(out) if raw else None
+        polyspec_contract(self.handle, out.data_ptr(), rs.data_ptr() if raw else None)
+        return (out, rs) if raw else out
+
+    def backward(self, grad_out):
+        import torch
+        grad_out = grad_out.to(device=self.device, dtype=torch.float64).contiguous()
+        g = torch.empty((self.batch, self.N, self.N, self.N), dtype=torch.float32, device=self.device)
+        polyspec_backward(self.handle, grad_out.data_ptr(), g.data_ptr())
+        return g
+
+    def fields(self):
+        """A copy of the kept float32 shell fields [batch, n_shells, N, N, N]."""
+        import torch
+        ptr = polyspec_fields(self.handle)
+        shape = (self.batch, self.n_shells, self.N, self.N, self.N)
+        view = torch.as_tensor(_DeviceArray(ptr, shape, "<f4"), device=self.device)
+        return view.clone()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            polyspec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    """Describes library-owned device memory to torch without copying."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), True), "version": 2}
+
+
+def polyspectrum(delta, plan: Plan):
+    """B [batch, n_closing] (float64) of delta [batch, N, N, N]; differentiable for order 3."""
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            plan.shells(x.detach())
+            return plan.contract()
+
+        @staticmethod
+        def backward(ctx, g):
+            return plan.backward(g)
+
+    return _Fn.apply(delta)

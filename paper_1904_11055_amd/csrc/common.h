@@ -1,0 +1,56 @@
+// Shared device-side helpers for the polyspectrum kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ps {
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
+// multiply by +i (s > 0) or -i (s < 0)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul_i(cplx<T> a, int s) {
+  return s > 0 ? cplx<T>{-a.im, a.re} : cplx<T>{a.im, -a.re};
+}
+
+// Geometry of the pruned transforms.  The ball of modes with |q| < K_e is held in
+// a dense "box" of (2Kc+1) x (Kc+1) x (2Kc+1) complex values indexed
+// [a = q0 + Kc][c = q2][e = q1 + Kc] (half space q2 >= 0), Kc the largest integer
+// component below K_e.  Intermediates between 1-D passes:
+//   H1[z][x1][c][a]   (after the q1 -> x1 transform),  N * B2 * B0 values
+//   H2[z][x0][x1][c]  (after the q0 -> x0 transform),  N * N * B2 values
+// z enumerates (batch, shell) pairs of one launch: batch = z / spb, shell =
+// shell_base + z % spb (spb = shells per batch; spb = 0 means one unmasked field
+// per batch, batch = z, shell 0).
+struct Geom {
+  int N;
+  int Kc;
+  int B0;   // 2Kc+1 (also the q1 extent of the box)
+  int B2;   // Kc+1
+  int spb;
+  int shell_base;
+  int n_shells;
+};
+
+__device__ __forceinline__ int geom_shell(const Geom& g, int z) {
+  return g.spb > 0 ? g.shell_base + z % g.spb : 0;
+}
+__device__ __forceinline__ int geom_batch(const Geom& g, int z) {
+  return g.spb > 0 ? z / g.spb : z;
+}
+
+}  // namespace ps

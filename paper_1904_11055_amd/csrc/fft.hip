@@ -1,0 +1,656 @@
+// Pruned, batched 3-D FFT passes for shell fields (gfx950).
+//
+// A shell field d_s[x] = sum_q [s(q) = s] delta_hat[q] e^{+2 pi i q.x/N} is the
+// unnormalised inverse transform of the density restricted to one spherical shell
+// (the paper's I_k(x), Sec. 2; FFTW(I~) in Appendix A).  Only the ball |q| < K_e is
+// non-zero, so the inverse 3-D transform runs as three 1-D passes that never touch
+// the empty part of the spectrum:
+//   P1  q1 -> x1 on the (2Kc+1)(Kc+1) columns that meet the shell (masked gather),
+//   P2  q0 -> x0 on N (Kc+1) pencils,
+//   P3  q2 -> x2 complex-to-real on N^2 rows, two rows per complex transform.
+// The forward (real-to-complex) direction runs the same passes in reverse and keeps
+// only the ball (input transform) or only one shell's modes (adjoint).
+//
+// Every block transforms P pencils of length N held in LDS (pencil stride N+1 to
+// spread banks) with a Stockham autosort FFT of radix-8 stages plus one radix-4 or
+// radix-2 stage; twiddles exp(2 pi i e / N) come from a table computed on the host
+// in double precision.
+#include "common.h"
+
+namespace ps {
+
+constexpr int kFftThreads = 256;
+
+template <typename T>
+struct FftCfg;
+template <>
+struct FftCfg<float> {
+  static constexpr int kElems = 4096;  // complex values per block (32 KiB of LDS)
+};
+template <>
+struct FftCfg<double> {
+  static constexpr int kElems = 2048;  // 32 KiB of LDS
+};
+
+// ---------------------------------------------------------------------------
+// small DFTs, X[r] = sum_t x[t] exp(S * 2 pi i r t / R), S = +1 (inverse) or -1
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+  cplx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft4(cplx<T>& x0, cplx<T>& x1, cplx<T>& x2, cplx<T>& x3) {
+  cplx<T> a = cadd(x0, x2), b = csub(x0, x2);
+  cplx<T> c = cadd(x1, x3), d = cmul_i(csub(x1, x3), S);
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, d);
+  x3 = csub(b, d);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+  cplx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cplx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T, S>(e0, e1, e2, e3);
+  dft4<T, S>(o0, o1, o2, o3);
+  const T h = (T)0.70710678118654752440084436210484903928;
+  // w8^r = exp(S 2 pi i r / 8)
+  cplx<T> t1 = cmul(o1, cplx<T>{h, (T)S * h});
+  cplx<T> t2 = cmul_i(o2, S);
+  cplx<T> t3 = cmul(o3, cplx<T>{-h, (T)S * h});
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+template <typename T, int S, int R>
+__device__ __forceinline__ void dftR(cplx<T>* v) {
+  if constexpr (R == 2) dft2<T, S>(v);
+  else if constexpr (R == 4) dft4<T, S>(v[0], v[1], v[2], v[3]);
+  else dft8<T, S>(v);
+}
+
+// One Stockham stage of radix R over P pencils of length N stored with stride NS.
+// After the stage every run of p*R consecutive outputs is a finished sub-DFT.
+template <typename T, int N, int P, int NS, int R, int S>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int p, const cplx<T>* __restrict__ tw) {
+  constexpr int NB = N / R;
+  constexpr int BPT = (P * NB) / kFftThreads;
+  static_assert(BPT >= 1 && (P * NB) % kFftThreads == 0, "block shape");
+  cplx<T> v[BPT][R];
+  const int tid = threadIdx.x;
+  const int stride_e = N / (p * R);
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    const int b = tid + u * kFftThreads;
+    const int pen = b / NB, i = b % NB;
+    const int k = i & (p - 1);
+    const cplx<T>* base = buf + pen * NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cplx<T> x = base[i + r * NB];
+      if (r > 0 && p > 1) {
+        cplx<T> w = tw[k * r * stride_e];
+        if (S < 0) w.im = -w.im;
+        x = cmul(x, w);
+      }
+      v[u][r] = x;
+    }
+    dftR<T, S, R>(v[u]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    const int b = tid + u * kFftThreads;
+    const int pen = b / NB, i = b % NB;
+    const int k = i & (p - 1);
+    const int j = (i - k) * R + k;
+    cplx<T>* base = buf + pen * NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) base[j + r * p] = v[u][r];
+  }
+  __syncthreads();
+}
+
+// Full length-N transform of the P pencils in buf (caller has synchronised).
+template <typename T, int N, int P, int NS, int S>
+__device__ __forceinline__ void fft_block(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+  int p = 1;
+  constexpr int L2 = __builtin_ctz(N);
+  constexpr int N8 = L2 / 3;
+  constexpr int REM = L2 % 3;
+#pragma unroll
+  for (int s = 0; s < N8; ++s) {
+    fft_stage<T, N, P, NS, 8, S>(buf, p, tw);
+    p *= 8;
+  }
+  if constexpr (REM == 2) fft_stage<T, N, P, NS, 4, S>(buf, p, tw);
+  if constexpr (REM == 1) fft_stage<T, N, P, NS, 2, S>(buf, p, tw);
+}
+
+__device__ __forceinline__ int freq_of(int n, int N) { return n < N / 2 ? n : n - N; }
+
+// ---------------------------------------------------------------------------
+// Inverse direction (ball -> real grid)
+// ---------------------------------------------------------------------------
+
+// P1: columns (a, c) of the box, transform q1 -> x1, masked by shell s(z).
+// UNIT: the input is the unit shell (1 inside, 0 outside) instead of the box.
+// grid (ceil(B0/P), B2, nz)
+template <typename T, int N, bool UNIT>
+__global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restrict__ box,
+                                                      const int16_t* __restrict__ shell_of_q,
+                                                      const int* __restrict__ qmax,
+                                                      cplx<T>* __restrict__ H1,
+                                                      const cplx<T>* __restrict__ tw, Geom g) {
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const int s = geom_shell(g, z);
+  const int b = geom_batch(g, z);
+  const int a0 = blockIdx.x * P;
+  const int c = blockIdx.y;
+  const int Kc = g.Kc;
+  const int qm = qmax[s];
+  {
+    // columns of the block that miss the shell's outer sphere are never read by P2
+    const int qa = a0 - Kc, qb = min(a0 + P - 1, g.B0 - 1) - Kc;
+    const int qmin0 = (qa <= 0 && qb >= 0) ? 0 : min(qa * qa, qb * qb);
+    if (qmin0 + c * c > qm) return;
+  }
+  const size_t box_sz = (size_t)g.B0 * g.B2 * g.B0;
+  const cplx<float>* bx = box + (size_t)b * box_sz;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u / N, n = u % N;
+    const int a = a0 + pp;
+    const int q1 = freq_of(n, N);
+    cplx<T> val{(T)0, (T)0};
+    if (a < g.B0 && q1 >= -Kc && q1 <= Kc) {
+      const int q0 = a - Kc;
+      const int Q = q0 * q0 + q1 * q1 + c * c;
+      if (Q <= qm) {
+        const int sid = shell_of_q[Q];
+        const bool in = (s == 0) ? (sid > 0) : (sid == s);
+        if (in) {
+          if (UNIT) {
+            val.re = (T)1;
+          } else {
+            cplx<float> v = bx[((size_t)a * g.B2 + c) * g.B0 + (q1 + Kc)];
+            val.re = (T)v.re;
+            val.im = (T)v.im;
+          }
+        }
+      }
+    }
+    buf[pp * NS + n] = val;
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, +1>(buf, tw);
+  // store H1[z][x1][c][a0 + pp]
+  cplx<T>* out = H1 + (size_t)z * N * g.B2 * g.B0;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u % P, x1 = u / P;
+    const int a = a0 + pp;
+    if (a < g.B0) out[((size_t)x1 * g.B2 + c) * g.B0 + a] = buf[pp * NS + x1];
+  }
+}
+
+// P2: pencils (x1, c), transform q0 -> x0.  grid (ceil(B2/P), N, nz)
+template <typename T, int N>
+__global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict__ H1,
+                                                      const int* __restrict__ qmax,
+                                                      cplx<T>* __restrict__ H2,
+                                                      const cplx<T>* __restrict__ tw, Geom g) {
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const int s = geom_shell(g, z);
+  const int c0 = blockIdx.x * P;
+  const int x1 = blockIdx.y;
+  const int Kc = g.Kc;
+  const int qm = qmax[s];
+  if (c0 * c0 > qm) return;  // every column of this chunk lies outside the shell
+  const cplx<T>* in = H1 + (size_t)z * N * g.B2 * g.B0 + (size_t)x1 * g.B2 * g.B0;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u / N, n = u % N;
+    const int c = c0 + pp;
+    const int q0 = freq_of(n, N);
+    cplx<T> val{(T)0, (T)0};
+    if (c < g.B2 && q0 >= -Kc && q0 <= Kc && q0 * q0 + c * c <= qm)
+      val = in[(size_t)c * g.B0 + (q0 + Kc)];
+    buf[pp * NS + n] = val;
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, +1>(buf, tw);
+  cplx<T>* out = H2 + (size_t)z * N * N * g.B2;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u % P, x0 = u / P;
+    const int c = c0 + pp;
+    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * N + x1) * g.B2 + c] = buf[pp * NS + x0];
+  }
+}
+
+// Build the packed two-row spectrum Z = A + iB of rows A, B (half spectra with
+// c <= cm, zero above) into an FFT pencil of length N.
+template <typename T>
+__device__ __forceinline__ cplx<T> two_row_spectrum(const cplx<T>* rowA, const cplx<T>* rowB, int n,
+                                                    int N, int cm) {
+  int c = n <= N / 2 ? n : N - n;
+  if (c > cm) return cplx<T>{(T)0, (T)0};
+  cplx<T> A = rowA[c], B = rowB[c];
+  if (c == 0) {  // the DC term of a real row is real
+    A.im = 0;
+    B.im = 0;
+  }
+  if (n > N / 2) {  // Z[-c] = conj(A[c]) + i conj(B[c])
+    A.im = -A.im;
+    B.im = -B.im;
+  }
+  return cplx<T>{A.re - B.im, A.im + B.re};
+}
+
+// P3 (full grid): rows (x0, x1) in pairs, complex-to-real over x2.
+// out[z * G + row * N + x2]; optional |value| maximum per z (as float bits).
+// grid (N*N/2/P, 1, nz)
+template <int N>
+__global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restrict__ H2,
+                                                      const int* __restrict__ qmax,
+                                                      float* __restrict__ out,
+                                                      unsigned* __restrict__ absmax,
+                                                      const cplx<float>* __restrict__ tw, Geom g) {
+  using T = float;
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const int s = geom_shell(g, z);
+  int cm = g.Kc;
+  {
+    const int qm = qmax[s];
+    while (cm * cm > qm) --cm;
+  }
+  const size_t G = (size_t)N * N * N;
+  const int row0 = blockIdx.x * 2 * P;  // first of the block's 2P rows
+  const cplx<T>* in = H2 + (size_t)z * N * N * g.B2 + (size_t)row0 * g.B2;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u / N, n = u % N;
+    buf[pp * NS + n] = two_row_spectrum<T>(in + (size_t)(2 * pp) * g.B2, in + (size_t)(2 * pp + 1) * g.B2, n, N, cm);
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, +1>(buf, tw);
+  float* o = out + (size_t)z * G + (size_t)row0 * N;
+  float amax = 0.f;
+#pragma unroll 4
+  for (int m = 0; m < 2 * E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;  // output index within the 2P rows
+    const int r = u / N, x2 = u % N;
+    const cplx<T> v = buf[(r >> 1) * NS + x2];
+    const float val = (r & 1) ? v.im : v.re;
+    o[u] = val;
+    amax = fmaxf(amax, fabsf(val));
+  }
+  if (absmax != nullptr) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(absmax + z, __float_as_uint(amax));
+  }
+}
+
+// P3 (symmetry wedge, float64): rows from a list, outputs x2 in [x1, N/2] only,
+// written compactly at out[z * nwedge + off(row) + x2 - x1].  rows[] holds
+// (x0, x1, off) triples; rows are processed two at a time.  grid (ceil(nrows/2/P), 1, nz)
+template <int N>
+__global__ __launch_bounds__(kFftThreads) void c2r_p3_wedge(const cplx<double>* __restrict__ H2,
+                                                            const int* __restrict__ qmax,
+                                                            const int* __restrict__ rows, int nrows,
+                                                            double* __restrict__ out, long long nwedge,
+                                                            const cplx<double>* __restrict__ tw,
+                                                            Geom g) {
+  using T = double;
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const int s = geom_shell(g, z);
+  int cm = g.Kc;
+  {
+    const int qm = qmax[s];
+    while (cm * cm > qm) --cm;
+  }
+  const int r0 = blockIdx.x * 2 * P;
+  const cplx<T>* in = H2 + (size_t)z * N * N * g.B2;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 2
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u / N, n = u % N;
+    const int ra = r0 + 2 * pp, rb = ra + 1;
+    cplx<T> v{0, 0};
+    if (ra < nrows) {
+      const cplx<T>* rowA = in + ((size_t)rows[3 * ra] * N + rows[3 * ra + 1]) * g.B2;
+      const cplx<T>* rowB = rb < nrows ? in + ((size_t)rows[3 * rb] * N + rows[3 * rb + 1]) * g.B2 : nullptr;
+      if (rowB != nullptr) {
+        v = two_row_spectrum<T>(rowA, rowB, n, N, cm);
+      } else {
+        v = two_row_spectrum<T>(rowA, rowA, n, N, cm);  // imaginary output unused
+      }
+    }
+    buf[pp * NS + n] = v;
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, +1>(buf, tw);
+  double* o = out + (size_t)z * nwedge;
+  for (int u = threadIdx.x; u < 2 * P * (N / 2 + 1); u += kFftThreads) {
+    const int r = u / (N / 2 + 1), x2 = u % (N / 2 + 1);
+    const int rr = r0 + r;
+    if (rr >= nrows) continue;
+    const int x1 = rows[3 * rr + 1], off = rows[3 * rr + 2];
+    if (x2 < x1) continue;
+    const cplx<T> v = buf[(r >> 1) * NS + x2];
+    o[off + x2 - x1] = (r & 1) ? v.im : v.re;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward direction (real grid -> ball)
+// ---------------------------------------------------------------------------
+
+// Q3: rows in pairs, real-to-complex over x2, keep c = 0..Kc.  in[z * G + row * N + x2].
+// grid (N*N/2/P, 1, nz)
+template <int N>
+__global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ in,
+                                                      cplx<float>* __restrict__ H2,
+                                                      const cplx<float>* __restrict__ tw, Geom g) {
+  using T = float;
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const size_t G = (size_t)N * N * N;
+  const int row0 = blockIdx.x * 2 * P;
+  const float* src = in + (size_t)z * G + (size_t)row0 * N;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;  // pencil pp = u / N, position x2
+    const int pp = u / N, x2 = u % N;
+    buf[pp * NS + x2] = cplx<T>{src[(size_t)(2 * pp) * N + x2], src[(size_t)(2 * pp + 1) * N + x2]};
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, -1>(buf, tw);
+  cplx<T>* o = H2 + (size_t)z * N * N * g.B2 + (size_t)row0 * g.B2;
+  for (int u = threadIdx.x; u < 2 * P * g.B2; u += kFftThreads) {
+    const int r = u / g.B2, c = u % g.B2;
+    const int pp = r >> 1;
+    const cplx<T> Zp = buf[pp * NS + c];
+    const cplx<T> Zm = buf[pp * NS + ((N - c) & (N - 1))];
+    cplx<T> v;
+    if ((r & 1) == 0) {  // A = (Z[c] + conj(Z[-c])) / 2
+      v = cplx<T>{(T)0.5 * (Zp.re + Zm.re), (T)0.5 * (Zp.im - Zm.im)};
+    } else {  // B = (Z[c] - conj(Z[-c])) / (2i)
+      v = cplx<T>{(T)0.5 * (Zp.im + Zm.im), (T)0.5 * (Zm.re - Zp.re)};
+    }
+    o[u] = v;
+  }
+}
+
+// Q2: pencils (x1, c), transform x0 -> q0, keep |q0| <= Kc.  grid (ceil(B2/P), N, nz)
+template <int N>
+__global__ __launch_bounds__(kFftThreads) void r2c_q2(const cplx<float>* __restrict__ H2,
+                                                      cplx<float>* __restrict__ H1,
+                                                      const cplx<float>* __restrict__ tw, Geom g) {
+  using T = float;
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const int c0 = blockIdx.x * P;
+  const int x1 = blockIdx.y;
+  const cplx<T>* in = H2 + (size_t)z * N * N * g.B2;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u % P, x0 = u / P;
+    const int c = c0 + pp;
+    buf[pp * NS + x0] = (c < g.B2) ? in[((size_t)x0 * N + x1) * g.B2 + c] : cplx<T>{0, 0};
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, -1>(buf, tw);
+  cplx<T>* o = H1 + (size_t)z * N * g.B2 * g.B0 + (size_t)x1 * g.B2 * g.B0;
+  for (int u = threadIdx.x; u < P * g.B0; u += kFftThreads) {
+    const int pp = u / g.B0, a = u % g.B0;
+    const int c = c0 + pp;
+    if (c >= g.B2) continue;
+    const int q0 = a - g.Kc;
+    o[(size_t)c * g.B0 + a] = buf[pp * NS + (q0 & (N - 1))];
+  }
+}
+
+// Q1: pencils (a, c), transform x1 -> q1, keep |q1| <= Kc and write into the box.
+// MASK: write only the modes of shell s(z) (other box entries untouched);
+// otherwise write every box entry of the column (the input transform).
+// grid (ceil(B0/P), B2, nz)
+template <int N, bool MASK>
+__global__ __launch_bounds__(kFftThreads) void r2c_q1(const cplx<float>* __restrict__ H1,
+                                                      const int16_t* __restrict__ shell_of_q,
+                                                      const int* __restrict__ qmax,
+                                                      cplx<float>* __restrict__ box,
+                                                      const cplx<float>* __restrict__ tw, Geom g) {
+  using T = float;
+  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int NS = N + 1;
+  __shared__ cplx<T> buf[P * NS];
+  const int z = blockIdx.z;
+  const int s = geom_shell(g, z);
+  const int b = geom_batch(g, z);
+  const int a0 = blockIdx.x * P;
+  const int c = blockIdx.y;
+  const int Kc = g.Kc;
+  const int qm = qmax[s];
+  if (MASK) {
+    // skip the block when none of its columns reaches shell s
+    const int qa = a0 - Kc, qb = a0 + P - 1 - Kc;
+    const int qmin0 = (qa <= 0 && qb >= 0) ? 0 : min(qa * qa, qb * qb);
+    if (qmin0 + c * c > qm) return;
+  }
+  const cplx<T>* in = H1 + (size_t)z * N * g.B2 * g.B0;
+  constexpr int E = P * N / kFftThreads;
+#pragma unroll 4
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u % P, x1 = u / P;
+    const int a = a0 + pp;
+    buf[pp * NS + x1] = (a < g.B0) ? in[((size_t)x1 * g.B2 + c) * g.B0 + a] : cplx<T>{0, 0};
+  }
+  __syncthreads();
+  fft_block<T, N, P, NS, -1>(buf, tw);
+  cplx<float>* o = box + (size_t)b * g.B0 * g.B2 * g.B0;
+  for (int u = threadIdx.x; u < P * g.B0; u += kFftThreads) {
+    const int pp = u / g.B0, e = u % g.B0;
+    const int a = a0 + pp;
+    if (a >= g.B0) continue;
+    const int q0 = a - Kc, q1 = e - Kc;
+    const int Q = q0 * q0 + q1 * q1 + c * c;
+    const size_t idx = ((size_t)a * g.B2 + c) * g.B0 + e;
+    const cplx<T> v = buf[pp * NS + (q1 & (N - 1))];
+    if (MASK) {
+      if (Q <= qm && shell_of_q[Q] == s) o[idx] = v;
+    } else {
+      o[idx] = v;
+    }
+  }
+}
+
+// Gather the box from a caller's half spectrum complex64 [batch][N][N][N/2+1].
+__global__ void box_from_half_spectrum(const cplx<float>* __restrict__ hs, cplx<float>* __restrict__ box,
+                                       Geom g) {
+  const int N = g.N;
+  const size_t box_sz = (size_t)g.B0 * g.B2 * g.B0;
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= box_sz) return;
+  const int e = i % g.B0;
+  const int c = (i / g.B0) % g.B2;
+  const int a = i / ((size_t)g.B0 * g.B2);
+  const int q0 = a - g.Kc, q1 = e - g.Kc;
+  const size_t src = (((size_t)(q0 & (N - 1)) * N) + (q1 & (N - 1))) * (N / 2 + 1) + c;
+  box[b * box_sz + i] = hs[(size_t)b * N * N * (N / 2 + 1) + src];
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+int fft_pencils_per_block(int N) { return FftCfg<T>::kElems / N; }
+
+#define PS_FOR_EACH_N(M) M(16) M(32) M(64) M(128) M(256) M(512) M(1024)
+
+template <typename T, bool UNIT>
+hipError_t launch_c2r_p1(const cplx<float>* box, const int16_t* sq, const int* qmax, cplx<T>* H1,
+                         const cplx<T>* tw, Geom g, int nz, hipStream_t st) {
+  const int P = FftCfg<T>::kElems / g.N;
+  dim3 grid((g.B0 + P - 1) / P, g.B2, nz);
+  switch (g.N) {
+#define CASE(n) \
+  case n: hipLaunchKernelGGL((c2r_p1<T, n, UNIT>), grid, dim3(kFftThreads), 0, st, box, sq, qmax, H1, tw, g); break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_c2r_p2(const cplx<T>* H1, const int* qmax, cplx<T>* H2, const cplx<T>* tw, Geom g, int nz,
+                         hipStream_t st) {
+  const int P = FftCfg<T>::kElems / g.N;
+  dim3 grid((g.B2 + P - 1) / P, g.N, nz);
+  switch (g.N) {
+#define CASE(n) case n: hipLaunchKernelGGL((c2r_p2<T, n>), grid, dim3(kFftThreads), 0, st, H1, qmax, H2, tw, g); break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_c2r_p3(const cplx<float>* H2, const int* qmax, float* out, unsigned* absmax,
+                         const cplx<float>* tw, Geom g, int nz, hipStream_t st) {
+  const int P = FftCfg<float>::kElems / g.N;
+  dim3 grid(g.N * g.N / 2 / P, 1, nz);
+  switch (g.N) {
+#define CASE(n) \
+  case n: hipLaunchKernelGGL((c2r_p3<n>), grid, dim3(kFftThreads), 0, st, H2, qmax, out, absmax, tw, g); break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_c2r_p3_wedge(const cplx<double>* H2, const int* qmax, const int* rows, int nrows,
+                               double* out, long long nwedge, const cplx<double>* tw, Geom g, int nz,
+                               hipStream_t st) {
+  const int P = FftCfg<double>::kElems / g.N;
+  dim3 grid((nrows + 2 * P - 1) / (2 * P), 1, nz);
+  switch (g.N) {
+#define CASE(n)                                                                                       \
+  case n:                                                                                             \
+    hipLaunchKernelGGL((c2r_p3_wedge<n>), grid, dim3(kFftThreads), 0, st, H2, qmax, rows, nrows, out, \
+                       nwedge, tw, g);                                                                \
+    break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_r2c_q3(const float* in, cplx<float>* H2, const cplx<float>* tw, Geom g, int nz,
+                         hipStream_t st) {
+  const int P = FftCfg<float>::kElems / g.N;
+  dim3 grid(g.N * g.N / 2 / P, 1, nz);
+  switch (g.N) {
+#define CASE(n) case n: hipLaunchKernelGGL((r2c_q3<n>), grid, dim3(kFftThreads), 0, st, in, H2, tw, g); break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_r2c_q2(const cplx<float>* H2, cplx<float>* H1, const cplx<float>* tw, Geom g, int nz,
+                         hipStream_t st) {
+  const int P = FftCfg<float>::kElems / g.N;
+  dim3 grid((g.B2 + P - 1) / P, g.N, nz);
+  switch (g.N) {
+#define CASE(n) case n: hipLaunchKernelGGL((r2c_q2<n>), grid, dim3(kFftThreads), 0, st, H2, H1, tw, g); break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <bool MASK>
+hipError_t launch_r2c_q1(const cplx<float>* H1, const int16_t* sq, const int* qmax, cplx<float>* box,
+                         const cplx<float>* tw, Geom g, int nz, hipStream_t st) {
+  const int P = FftCfg<float>::kElems / g.N;
+  dim3 grid((g.B0 + P - 1) / P, g.B2, nz);
+  switch (g.N) {
+#define CASE(n) \
+  case n: hipLaunchKernelGGL((r2c_q1<n, MASK>), grid, dim3(kFftThreads), 0, st, H1, sq, qmax, box, tw, g); break;
+    PS_FOR_EACH_N(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_box_from_half_spectrum(const cplx<float>* hs, cplx<float>* box, Geom g, int batch,
+                                         hipStream_t st) {
+  const size_t box_sz = (size_t)g.B0 * g.B2 * g.B0;
+  dim3 grid((unsigned)((box_sz + 255) / 256), batch);
+  hipLaunchKernelGGL(box_from_half_spectrum, grid, dim3(256), 0, st, hs, box, g);
+  return hipGetLastError();
+}
+
+template hipError_t launch_c2r_p1<float, false>(const cplx<float>*, const int16_t*, const int*, cplx<float>*,
+                                                const cplx<float>*, Geom, int, hipStream_t);
+template hipError_t launch_c2r_p1<double, true>(const cplx<float>*, const int16_t*, const int*, cplx<double>*,
+                                                const cplx<double>*, Geom, int, hipStream_t);
+template hipError_t launch_c2r_p2<float>(const cplx<float>*, const int*, cplx<float>*, const cplx<float>*, Geom,
+                                         int, hipStream_t);
+template hipError_t launch_c2r_p2<double>(const cplx<double>*, const int*, cplx<double>*, const cplx<double>*,
+                                          Geom, int, hipStream_t);
+template hipError_t launch_r2c_q1<true>(const cplx<float>*, const int16_t*, const int*, cplx<float>*,
+                                        const cplx<float>*, Geom, int, hipStream_t);
+template hipError_t launch_r2c_q1<false>(const cplx<float>*, const int16_t*, const int*, cplx<float>*,
+                                         const cplx<float>*, Geom, int, hipStream_t);
+
+}  // namespace ps

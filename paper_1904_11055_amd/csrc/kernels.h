@@ -1,0 +1,77 @@
+// Host-side launchers of the device kernels (fft.hip, contract.hip, util.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace ps {
+
+// fft.hip
+template <typename T>
+int fft_pencils_per_block(int N);
+template <typename T, bool UNIT>
+hipError_t launch_c2r_p1(const cplx<float>* box, const int16_t* shell_of_q, const int* qmax, cplx<T>* H1,
+                         const cplx<T>* tw, Geom g, int nz, hipStream_t st);
+template <typename T>
+hipError_t launch_c2r_p2(const cplx<T>* H1, const int* qmax, cplx<T>* H2, const cplx<T>* tw, Geom g, int nz,
+                         hipStream_t st);
+hipError_t launch_c2r_p3(const cplx<float>* H2, const int* qmax, float* out, unsigned* absmax,
+                         const cplx<float>* tw, Geom g, int nz, hipStream_t st);
+hipError_t launch_c2r_p3_wedge(const cplx<double>* H2, const int* qmax, const int* rows, int nrows, double* out,
+                               long long nwedge, const cplx<double>* tw, Geom g, int nz, hipStream_t st);
+hipError_t launch_r2c_q3(const float* in, cplx<float>* H2, const cplx<float>* tw, Geom g, int nz, hipStream_t st);
+hipError_t launch_r2c_q2(const cplx<float>* H2, cplx<float>* H1, const cplx<float>* tw, Geom g, int nz,
+                         hipStream_t st);
+template <bool MASK>
+hipError_t launch_r2c_q1(const cplx<float>* H1, const int16_t* shell_of_q, const int* qmax, cplx<float>* box,
+                         const cplx<float>* tw, Geom g, int nz, hipStream_t st);
+hipError_t launch_box_from_half_spectrum(const cplx<float>* hs, cplx<float>* box, Geom g, int batch,
+                                         hipStream_t st);
+
+// contract.hip
+struct CtrParams {
+  const float* D;
+  const int* pair_uv;
+  const int* slots;
+  const int* slot_tile;
+  const unsigned* absmax;
+  float* partials;
+  long long G;
+  int n_shells;
+  int n_blk;
+  int n_pairs_padded;
+  int n_tiles;
+  int ksteps;
+  int n_chunks;
+};
+constexpr int kCtrWavesHost = 8;
+constexpr int kSlotsHost = 32;
+constexpr int kMaxBlkHost = 4;
+constexpr int kAdjPtsHost = 128;
+constexpr int kCntTuplesPerGroup = 1024;
+constexpr int kCntStageHost = 32;
+
+hipError_t launch_contract(int prec, int order, const CtrParams& p, int n_groups, int batch, hipStream_t st);
+hipError_t launch_reduce_f32(const float* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
+                             int batch, hipStream_t st);
+hipError_t launch_reduce_f64(const double* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
+                             int batch, hipStream_t st);
+hipError_t launch_gather(const double* tmp, int n_groups, long long n_ent, const int* ent_idx, const int* bins,
+                         int order, const double* fnorm, int n_closing, const unsigned* absmax, int n_shells,
+                         int prec, double* out, double* raw, int* nonfinite, int batch, hipStream_t st);
+hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, const unsigned char* wmult,
+                               const int* cand, int n_cand, int n_shells, int stages_per_chunk, int n_chunks,
+                               double* part, hipStream_t st);
+hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, const int* pair_uv,
+                                  int n_pairs, int n_pairs_padded, int n_shells, int n_closing, float* W, int batch,
+                                  hipStream_t st);
+hipError_t launch_adjoint_gemm(int prec, const float* D, const float* W, const unsigned char* wmask,
+                               const int* pair_uv, int n_pairs_padded, int n_shells, int n_blk, long long G,
+                               float* A, int batch, hipStream_t st);
+
+// util.hip
+hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_t st);
+
+}  // namespace ps

@@ -1,0 +1,850 @@
+// Host side of the polyspectrum library: descriptor validation, shell and tuple
+// tables, tile scheduling, workspace, plan-time polygon counts and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/polyspec.h"
+#include "kernels.h"
+
+using ps::cplx;
+using ps::Geom;
+
+namespace {
+
+thread_local std::string g_plan_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+// Exact dyadic representation of the shell width: width = m * 2^e with m odd.
+struct Dyadic {
+  int64_t m = 0;
+  int e = 0;
+};
+
+bool to_dyadic(double w, Dyadic* out) {
+  if (!(w > 0.0) || !std::isfinite(w)) return false;
+  int ex = 0;
+  double fr = std::frexp(w, &ex);            // w = fr * 2^ex, fr in [0.5, 1)
+  double mm = std::ldexp(fr, 53);            // integer
+  int64_t m = (int64_t)mm;
+  int e = ex - 53;
+  while ((m & 1) == 0) {
+    m >>= 1;
+    ++e;
+  }
+  out->m = m;
+  out->e = e;
+  return true;
+}
+
+using u128 = unsigned __int128;
+
+// Smallest integer Q with 4 Q >= (k * width)^2, k >= 1 odd; width = m 2^e, m < 2^24.
+int64_t ceil_quarter_square(int64_t k, const Dyadic& d) {
+  u128 num = (u128)(k * d.m) * (u128)(k * d.m);  // (k m)^2 < 2^70
+  int sh = 2 * d.e - 2;                            // Q >= num * 2^(2e) / 4
+  if (sh >= 0) return (int64_t)(num << sh);
+  int r = -sh;
+  if (r >= 127) return num ? 1 : 0;
+  u128 q = num >> r;
+  if ((q << r) != num) ++q;
+  return (int64_t)q;
+}
+
+}  // namespace
+
+struct polyspec_plan_s {
+  polyspec_desc desc{};
+  hipStream_t stream = nullptr;
+  std::string last_error;
+
+  int N = 0, order = 0, nb = 0, batch = 0, prec = 0;
+  int Kc = 0, B0 = 0, B2 = 0, n_blk = 0;
+  long long G = 0;
+  bool alias_free = true;
+
+  std::vector<int64_t> thr;        // T_1..T_{nb+1}
+  std::vector<int16_t> shell_of_q;
+  std::vector<int> qmax;           // [nb+1]
+
+  // tuples (0-based shells)
+  std::vector<int> cand;           // [n_cand][order]
+  std::vector<double> cand_quot;   // C_t / N^3
+  std::vector<int64_t> cand_count;
+  std::vector<int> closing;        // candidate index of each closing tuple
+  std::vector<int> cl_bins;        // [n_closing][order]
+  std::vector<int64_t> cl_counts;
+
+  // contraction tiling
+  int n_pairs = 0, n_pairs_padded = 0, n_tiles = 0, n_groups = 0, ksteps = 0, n_chunks = 0;
+  int red_groups = 0, red_cpg = 0;
+  std::vector<int> pair_uv;
+
+  // device tables
+  DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_tile_d, ent_d, bins_d, fnorm_d, lookup_d, wmask_d, flag_d;
+  // workspace carving
+  DevBuf own_ws;
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  cplx<float>* box = nullptr;
+  cplx<float>* gbox = nullptr;
+  cplx<float>* H1 = nullptr;
+  cplx<float>* H2 = nullptr;
+  float* D = nullptr;
+  float* A = nullptr;
+  float* partials = nullptr;
+  double* red = nullptr;
+  unsigned* absmax = nullptr;
+  float* W = nullptr;
+  bool have_fields = false;
+
+  polyspec_status fail(polyspec_status st, const std::string& msg) {
+    last_error = msg;
+    return st;
+  }
+};
+
+namespace {
+
+polyspec_status dev_alloc(polyspec_plan_s* p, DevBuf* b, size_t n) {
+  b->n = n;
+  if (n == 0) {
+    b->p = nullptr;
+    return POLYSPEC_OK;
+  }
+  hipError_t e = hipMalloc(&b->p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b->p = nullptr;
+    return p->fail(e == hipErrorOutOfMemory ? POLYSPEC_ERR_OUT_OF_MEMORY : POLYSPEC_ERR_DEVICE,
+                   std::string("hipMalloc of ") + std::to_string(n) + " bytes failed: " + hipGetErrorString(e));
+  }
+  return POLYSPEC_OK;
+}
+
+void dev_free(DevBuf* b) {
+  if (b->p) (void)hipFree(b->p);
+  b->p = nullptr;
+  b->n = 0;
+}
+
+template <typename T>
+polyspec_status upload(polyspec_plan_s* p, DevBuf* b, const std::vector<T>& v) {
+  polyspec_status st = dev_alloc(p, b, v.size() * sizeof(T));
+  if (st != POLYSPEC_OK || v.empty()) return st;
+  hipError_t e = hipMemcpy(b->p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return p->fail(POLYSPEC_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  return POLYSPEC_OK;
+}
+
+#define PS_HIP(p, ...)                                                                                     \
+  do {                                                                                                     \
+    hipError_t e_ = (__VA_ARGS__);                                                                            \
+    if (e_ != hipSuccess) {                                                                                \
+      (void)hipGetLastError();                                                                             \
+      return (p)->fail(POLYSPEC_ERR_DEVICE, std::string(#__VA_ARGS__) + " failed: " + hipGetErrorString(e_));     \
+    }                                                                                                      \
+  } while (0)
+
+#define PS_TRY(expr)                     \
+  do {                                   \
+    polyspec_status s_ = (expr);         \
+    if (s_ != POLYSPEC_OK) return s_;    \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Geom make_geom(const polyspec_plan_s* p, int spb, int shell_base) {
+  Geom g;
+  g.N = p->N;
+  g.Kc = p->Kc;
+  g.B0 = p->B0;
+  g.B2 = p->B2;
+  g.spb = spb;
+  g.shell_base = shell_base;
+  g.n_shells = p->nb;
+  return g;
+}
+
+template <typename T>
+std::vector<cplx<T>> twiddles(int N) {
+  std::vector<cplx<T>> tw(N);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int e = 0; e < N; ++e) {
+    long double a = two_pi * (long double)e / (long double)N;
+    tw[e].re = (T)std::cos(a);
+    tw[e].im = (T)std::sin(a);
+  }
+  // exact values on the axes and diagonals
+  for (int e = 0; e < N; e += N / 4) {
+    int q = e / (N / 4);
+    tw[e].re = (T)(q == 0 ? 1 : q == 2 ? -1 : 0);
+    tw[e].im = (T)(q == 1 ? 1 : q == 3 ? -1 : 0);
+  }
+  return tw;
+}
+
+// Sizes of the workspace pieces, in carving order.
+struct WsLayout {
+  size_t box, gbox, H1, H2, D, A, partials, red, absmax, W, total;
+};
+
+WsLayout layout_of(const polyspec_plan_s* p) {
+  WsLayout L{};
+  const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
+  const size_t zf = (size_t)p->batch * p->nb;
+  L.box = align256((size_t)p->batch * box_elems * sizeof(cplx<float>));
+  L.gbox = (p->order == 3) ? L.box : 0;
+  L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
+  L.H2 = align256(zf * p->N * p->N * p->B2 * sizeof(cplx<float>));
+  L.D = align256(zf * (size_t)p->G * sizeof(float));
+  L.A = (p->order == 3) ? L.D : 0;
+  L.partials = align256((size_t)p->batch * p->n_chunks * (size_t)p->n_tiles * 256 * sizeof(float));
+  L.red = align256((size_t)p->batch * p->red_groups * (size_t)p->n_tiles * 256 * sizeof(double));
+  L.absmax = align256(zf * sizeof(unsigned));
+  L.W = (p->order == 3) ? align256((size_t)p->batch * p->nb * p->n_pairs_padded * sizeof(float)) : 0;
+  L.total = L.box + L.gbox + L.H1 + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
+  return L;
+}
+
+void carve(polyspec_plan_s* p, char* base) {
+  WsLayout L = layout_of(p);
+  char* c = base;
+  p->box = (cplx<float>*)c; c += L.box;
+  p->gbox = L.gbox ? (cplx<float>*)c : nullptr; c += L.gbox;
+  p->H1 = (cplx<float>*)c; c += L.H1;
+  p->H2 = (cplx<float>*)c; c += L.H2;
+  p->D = (float*)c; c += L.D;
+  p->A = L.A ? (float*)c : nullptr; c += L.A;
+  p->partials = (float*)c; c += L.partials;
+  p->red = (double*)c; c += L.red;
+  p->absmax = (unsigned*)c; c += L.absmax;
+  p->W = L.W ? (float*)c : nullptr; c += L.W;
+}
+
+polyspec_status ensure_workspace(polyspec_plan_s* p) {
+  if (p->ws) return POLYSPEC_OK;
+  WsLayout L = layout_of(p);
+  PS_TRY(dev_alloc(p, &p->own_ws, L.total));
+  p->ws = (char*)p->own_ws.p;
+  p->ws_size = L.total;
+  carve(p, p->ws);
+  return POLYSPEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tables
+// ---------------------------------------------------------------------------
+void build_tuples(polyspec_plan_s* p) {
+  const int n = p->order, nb = p->nb;
+  std::vector<int> t(n, 0);
+  // lexicographic enumeration of t_0 <= ... <= t_{n-1}, last index fastest
+  while (true) {
+    bool ok = true;
+    if (p->alias_free) {
+      // 1-based: t_n < sum_{j<n} t_j + n/2  <=>  2 t_n < 2 sum + n
+      long long s = 0;
+      for (int j = 0; j < n - 1; ++j) s += t[j] + 1;
+      ok = 2LL * (t[n - 1] + 1) < 2 * s + n;
+    }
+    if (ok)
+      for (int j = 0; j < n; ++j) p->cand.push_back(t[j]);
+    int j = n - 1;
+    while (j >= 0 && t[j] == nb - 1) --j;
+    if (j < 0) break;
+    ++t[j];
+    for (int k = j + 1; k < n; ++k) t[k] = t[j];
+  }
+}
+
+// Pairs (i <= j) ordered by j, then i: a block of 16 consecutive pairs spans few
+// values of j, so few shell blocks k >= j close triangles with it.
+void build_pairs(polyspec_plan_s* p, std::vector<int>* pidx) {
+  const int nb = p->nb;
+  p->n_pairs = nb * (nb + 1) / 2;
+  p->n_pairs_padded = (p->n_pairs + 31) / 32 * 32;
+  const int zrow = p->n_blk * 16;
+  p->pair_uv.assign(p->n_pairs_padded, zrow | (zrow << 16));
+  pidx->assign(nb * nb, -1);
+  int k = 0;
+  for (int j = 0; j < nb; ++j)
+    for (int i = 0; i <= j; ++i) {
+      p->pair_uv[k] = i | (j << 16);
+      (*pidx)[i * nb + j] = k;
+      ++k;
+    }
+}
+
+struct TileKey {
+  int a, b;
+  bool operator<(const TileKey& o) const { return a != o.a ? a < o.a : b < o.b; }
+};
+
+// Entry of output (row, col) of a 16x16 tile in the dumped accumulator layout:
+// lane 16 (row / 4) + col, register row % 4.
+inline int tile_entry(int row, int col) { return 4 * (16 * (row / 4) + col) + (row % 4); }
+
+polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
+  std::vector<int> pidx;
+  build_pairs(p, &pidx);
+  const int n = p->order, nb = p->nb;
+  const size_t nc = p->cand.size() / n;
+  std::map<TileKey, int> tiles;
+  std::vector<std::array<int, 4>> loc(nc);  // ablk, bblk, row, col
+  for (size_t c = 0; c < nc; ++c) {
+    const int* t = &p->cand[c * n];
+    int ra, rb;
+    if (n == 2) {
+      ra = t[0];
+      rb = t[1];
+    } else if (n == 3) {
+      ra = pidx[t[0] * nb + t[1]];
+      rb = t[2];
+    } else {
+      ra = pidx[t[0] * nb + t[1]];
+      rb = pidx[t[2] * nb + t[3]];
+    }
+    loc[c] = {ra / 16, rb / 16, ra % 16, rb % 16};
+    tiles[TileKey{ra / 16, rb / 16}] = 0;
+  }
+  int id = 0;
+  std::vector<TileKey> tlist;
+  for (auto& kv : tiles) {
+    kv.second = id++;
+    tlist.push_back(kv.first);
+  }
+  p->n_tiles = id;
+  ent_of_cand->resize(nc);
+  for (size_t c = 0; c < nc; ++c) {
+    const int t = tiles[TileKey{loc[c][0], loc[c][1]}];
+    (*ent_of_cand)[c] = t * 256 + tile_entry(loc[c][2], loc[c][3]);
+  }
+  // units: runs of tiles sharing the A block
+  std::vector<std::pair<int, int>> units;  // [first tile, count]
+  for (int t = 0; t < id;) {
+    int u = t;
+    while (u < id && tlist[u].a == tlist[t].a) ++u;
+    units.push_back({t, u - t});
+    t = u;
+  }
+  // greedy: largest units first, onto the least loaded wave with room
+  std::vector<int> order(units.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return units[x].second > units[y].second; });
+  struct Wave {
+    std::vector<int> tiles;
+    double load = 0;
+  };
+  std::vector<std::vector<Wave>> groups;
+  auto new_group = [&]() { groups.emplace_back(ps::kCtrWavesHost); };
+  new_group();
+  const double form_cost = 1.0, tile_cost = 1.0;
+  for (int ui : order) {
+    const int cnt = units[ui].second;
+    if (cnt > ps::kSlotsHost) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "tile unit larger than a wave");
+    Wave* best = nullptr;
+    for (auto& grp : groups)
+      for (auto& w : grp)
+        if ((int)w.tiles.size() + cnt <= ps::kSlotsHost && (!best || w.load < best->load)) best = &w;
+    if (!best) {
+      new_group();
+      best = &groups.back()[0];
+    }
+    for (int k = 0; k < cnt; ++k) best->tiles.push_back(units[ui].first + k);
+    best->load += form_cost + tile_cost * cnt * (n == 4 ? 2.0 : 1.0);
+  }
+  p->n_groups = (int)groups.size();
+  std::vector<int> slots(p->n_groups * ps::kCtrWavesHost * ps::kSlotsHost, -1);
+  std::vector<int> slot_tile(slots.size(), -1);
+  for (int gi = 0; gi < p->n_groups; ++gi)
+    for (int w = 0; w < ps::kCtrWavesHost; ++w) {
+      auto& tl = groups[gi][w].tiles;
+      std::sort(tl.begin(), tl.end());
+      int prev_a = -1;
+      for (size_t s = 0; s < tl.size(); ++s) {
+        const TileKey k = tlist[tl[s]];
+        int word = (k.a & 0xfff) | ((k.b & 0xfff) << 12);
+        if (k.a != prev_a) word |= 1 << 24;
+        prev_a = k.a;
+        const size_t at = ((size_t)gi * ps::kCtrWavesHost + w) * ps::kSlotsHost + s;
+        slots[at] = word;
+        slot_tile[at] = tl[s];
+      }
+    }
+  PS_TRY(upload(p, &p->slots_d, slots));
+  PS_TRY(upload(p, &p->slot_tile_d, slot_tile));
+  PS_TRY(upload(p, &p->pairs_d, p->pair_uv));
+  return POLYSPEC_OK;
+}
+
+// Plan-time counts: unit-shell fields in float64 on the symmetry wedge, then
+// C_t = sum over the wedge of orbit size times the product.
+polyspec_status compute_counts(polyspec_plan_s* p) {
+  const int N = p->N, h = N / 2, nb = p->nb, n = p->order;
+  std::vector<int> rows;
+  std::vector<unsigned char> wmult;
+  long long off = 0;
+  for (int x0 = 0; x0 <= h; ++x0)
+    for (int x1 = x0; x1 <= h; ++x1) {
+      rows.push_back(x0);
+      rows.push_back(x1);
+      rows.push_back((int)off);
+      for (int x2 = x1; x2 <= h; ++x2) {
+        int signs = (x0 != 0 && x0 != h ? 2 : 1) * (x1 != 0 && x1 != h ? 2 : 1) * (x2 != 0 && x2 != h ? 2 : 1);
+        int perms = (x0 == x1 && x1 == x2) ? 1 : (x0 == x1 || x1 == x2) ? 3 : 6;
+        wmult.push_back((unsigned char)(signs * perms));
+      }
+      off += h - x1 + 1;
+    }
+  const long long nwedge = off;
+  const int nrows = (int)(rows.size() / 3);
+  const size_t n_cand = p->cand.size() / n;
+
+  DevBuf tw64, rows_d, wm_d, cand_d, cw, H1d, H2d, part, tmp;
+  auto cleanup = [&]() {
+    dev_free(&tw64); dev_free(&rows_d); dev_free(&wm_d); dev_free(&cand_d); dev_free(&cw);
+    dev_free(&H1d); dev_free(&H2d); dev_free(&part); dev_free(&tmp);
+  };
+  polyspec_status st = POLYSPEC_OK;
+  do {
+    if ((st = upload(p, &tw64, twiddles<double>(N))) != POLYSPEC_OK) break;
+    if ((st = upload(p, &rows_d, rows)) != POLYSPEC_OK) break;
+    if ((st = upload(p, &wm_d, wmult)) != POLYSPEC_OK) break;
+    if ((st = upload(p, &cand_d, p->cand)) != POLYSPEC_OK) break;
+    if ((st = dev_alloc(p, &cw, (size_t)nb * nwedge * sizeof(double))) != POLYSPEC_OK) break;
+    // shells per group: keep the float64 intermediates near 4 GiB
+    const size_t per_shell = ((size_t)N * p->B2 * p->B0 + (size_t)N * N * p->B2) * sizeof(cplx<double>);
+    int gs = (int)std::max<size_t>(1, std::min<size_t>(nb, ((size_t)4 << 30) / std::max<size_t>(per_shell, 1)));
+    gs = std::max(1, std::min(gs, nb));
+    if ((st = dev_alloc(p, &H1d, (size_t)gs * N * p->B2 * p->B0 * sizeof(cplx<double>))) != POLYSPEC_OK) break;
+    if ((st = dev_alloc(p, &H2d, (size_t)gs * N * N * p->B2 * sizeof(cplx<double>))) != POLYSPEC_OK) break;
+    hipError_t e = hipSuccess;
+    for (int s0 = 0; s0 < nb && e == hipSuccess; s0 += gs) {
+      const int cnt = std::min(gs, nb - s0);
+      Geom g = make_geom(p, cnt, s0 + 1);
+      e = ps::launch_c2r_p1<double, true>(nullptr, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p,
+                                          (cplx<double>*)H1d.p, (const cplx<double>*)tw64.p, g, cnt, p->stream);
+      if (e == hipSuccess)
+        e = ps::launch_c2r_p2<double>((const cplx<double>*)H1d.p, (const int*)p->qmax_d.p, (cplx<double>*)H2d.p,
+                                      (const cplx<double>*)tw64.p, g, cnt, p->stream);
+      if (e == hipSuccess)
+        e = ps::launch_c2r_p3_wedge((const cplx<double>*)H2d.p, (const int*)p->qmax_d.p, (const int*)rows_d.p,
+                                    nrows, (double*)cw.p + (size_t)s0 * nwedge, nwedge,
+                                    (const cplx<double>*)tw64.p, g, cnt, p->stream);
+    }
+    if (e != hipSuccess) {
+      st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count-field transform: ") + hipGetErrorString(e));
+      break;
+    }
+    dev_free(&H1d);
+    dev_free(&H2d);
+    // contraction over the wedge
+    const int spc = 64;  // 32-point stages per chunk: 2048 wedge points
+    const long long pts_per_chunk = (long long)spc * ps::kCntStageHost;
+    const int n_chunks = (int)((nwedge + pts_per_chunk - 1) / pts_per_chunk);
+    if ((st = dev_alloc(p, &part, (size_t)n_chunks * n_cand * sizeof(double))) != POLYSPEC_OK) break;
+    e = ps::launch_counts_wedge(n, (const double*)cw.p, nwedge, (const unsigned char*)wm_d.p, (const int*)cand_d.p,
+                                (int)n_cand, nb, spc, n_chunks, (double*)part.p, p->stream);
+    if (e != hipSuccess) {
+      st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count contraction: ") + hipGetErrorString(e));
+      break;
+    }
+    const int cpg = 64;
+    const int ngr = (n_chunks + cpg - 1) / cpg;
+    if ((st = dev_alloc(p, &tmp, (size_t)ngr * n_cand * sizeof(double))) != POLYSPEC_OK) break;
+    e = ps::launch_reduce_f64((const double*)part.p, (double*)tmp.p, n_chunks, cpg, ngr, (long long)n_cand, 1,
+                              p->stream);
+    if (e != hipSuccess) {
+      st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count reduction: ") + hipGetErrorString(e));
+      break;
+    }
+    std::vector<double> host((size_t)ngr * n_cand);
+    e = hipMemcpyAsync(host.data(), tmp.p, host.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+      st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count readback: ") + hipGetErrorString(e));
+      break;
+    }
+    const double N3 = (double)N * N * N;
+    p->cand_quot.assign(n_cand, 0.0);
+    p->cand_count.assign(n_cand, 0);
+    double worst = 0.0;
+    size_t worst_at = 0;
+    for (size_t c = 0; c < n_cand; ++c) {
+      double s = 0.0;
+      for (int gi = 0; gi < ngr; ++gi) s += host[(size_t)gi * n_cand + c];
+      const double q = s / N3;
+      const double r = std::rint(q);
+      p->cand_quot[c] = q;
+      p->cand_count[c] = (int64_t)r;
+      if (std::fabs(q - r) > worst) {
+        worst = std::fabs(q - r);
+        worst_at = c;
+      }
+    }
+    if (!(worst < 1e-3)) {
+      st = p->fail(POLYSPEC_ERR_COUNT_NOT_INTEGRAL,
+                   "polygon count quotient " + std::to_string(p->cand_quot[worst_at]) + " of candidate " +
+                       std::to_string(worst_at) + " is not within 1e-3 of an integer");
+      break;
+    }
+  } while (false);
+  cleanup();
+  return st;
+}
+
+polyspec_status build_plan(polyspec_plan_s* p) {
+  const polyspec_desc& d = p->desc;
+  if (d.N < 32 || d.N > 1024 || (d.N & (d.N - 1)) != 0)
+    return p->fail(POLYSPEC_ERR_INVALID_ARG, "N must be a power of two in [32, 1024]");
+  if (d.order < 2 || d.order > 4) return p->fail(POLYSPEC_ERR_INVALID_ARG, "order must be 2, 3 or 4");
+  if (d.n_shells < 1) return p->fail(POLYSPEC_ERR_INVALID_ARG, "n_shells must be >= 1");
+  if (d.batch < 1) return p->fail(POLYSPEC_ERR_INVALID_ARG, "batch must be >= 1");
+  if (d.precision < 0 || d.precision > 2) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown precision");
+  if (!(d.box_length >= 0.0) || !std::isfinite(d.box_length))
+    return p->fail(POLYSPEC_ERR_INVALID_ARG, "box_length must be finite and >= 0");
+  const uint32_t known = POLYSPEC_INPUT_HALF_SPECTRUM | POLYSPEC_ALLOW_ALIASING | POLYSPEC_NAN_GUARD;
+  if (d.flags & ~known) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown flag bits");
+  Dyadic w;
+  if (!to_dyadic(d.shell_width, &w)) return p->fail(POLYSPEC_ERR_INVALID_ARG, "shell_width must be finite and > 0");
+  if (w.m >= (1LL << 24) || w.e < -40 || w.e > 20)
+    return p->fail(POLYSPEC_ERR_INVALID_ARG, "shell_width must be a binary fraction with at most 24 significant bits");
+  p->N = d.N;
+  p->order = d.order;
+  p->nb = d.n_shells;
+  p->batch = d.batch;
+  p->prec = d.precision;
+  p->G = (long long)d.N * d.N * d.N;
+  // (2 nb + 1) width <= N: the last shell's outer edge stays below Nyquist
+  {
+    const long double ke2 = (long double)(2 * d.n_shells + 1) * (long double)d.shell_width;
+    if (ke2 > (long double)d.N)
+      return p->fail(POLYSPEC_ERR_INVALID_ARG, "(n_shells + 1/2) * shell_width exceeds N/2");
+    const long double alias = (long double)d.order * ke2;
+    p->alias_free = alias <= 2.0L * (long double)d.N;
+    if (!p->alias_free && !(d.flags & POLYSPEC_ALLOW_ALIASING))
+      return p->fail(POLYSPEC_ERR_ALIASING,
+                     "order * (n_shells + 1/2) * shell_width > N; set POLYSPEC_ALLOW_ALIASING for the mod-N estimator");
+  }
+  if (d.n_shells > 16 * ps::kMaxBlkHost)
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "the matrix-core contraction handles at most 64 shells");
+  if ((d.flags & POLYSPEC_INPUT_HALF_SPECTRUM) && (d.N * (size_t)d.N * (d.N / 2 + 1)) == 0)
+    return p->fail(POLYSPEC_ERR_INVALID_ARG, "bad half-spectrum size");
+
+  // shell thresholds: shell s (1-based) holds T_s <= |q|^2 < T_{s+1}
+  p->thr.resize(p->nb + 1);
+  for (int s = 1; s <= p->nb + 1; ++s) p->thr[s - 1] = ceil_quarter_square(2 * s - 1, w);
+  const int64_t qtop = p->thr[p->nb] - 1;  // largest |q|^2 inside the ball
+  int Kc = 0;
+  while ((int64_t)(Kc + 1) * (Kc + 1) <= qtop) ++Kc;
+  p->Kc = Kc;
+  p->B0 = 2 * Kc + 1;
+  p->B2 = Kc + 1;
+  p->n_blk = (p->nb + 15) / 16;
+  const int64_t qtab = 3LL * Kc * Kc + 1;
+  p->shell_of_q.assign(qtab, 0);
+  for (int64_t Q = 0; Q < qtab; ++Q) {
+    int s = 0;
+    while (s < p->nb && p->thr[s] <= Q) ++s;  // s = number of thresholds <= Q
+    p->shell_of_q[Q] = (int16_t)((Q < p->thr[p->nb] && s >= 1) ? s : 0);
+  }
+  p->qmax.resize(p->nb + 1);
+  p->qmax[0] = (int)qtop;
+  for (int s = 1; s <= p->nb; ++s) p->qmax[s] = (int)(p->thr[s] - 1);
+
+  build_tuples(p);
+  std::vector<int> ent_of_cand;
+  PS_TRY(build_tiles(p, &ent_of_cand));
+
+  // chunking of the grid for the contraction
+  const long long steps = p->G / 32;
+  long long ks = steps / 512;
+  ks = std::max(1LL, std::min(256LL, ks));
+  while (steps % ks) --ks;
+  p->ksteps = (int)ks;
+  p->n_chunks = (int)(steps / ks);
+  p->red_cpg = 64;
+  p->red_groups = (p->n_chunks + p->red_cpg - 1) / p->red_cpg;
+
+  PS_TRY(upload(p, &p->tw32, twiddles<float>(p->N)));
+  PS_TRY(upload(p, &p->shell_q, p->shell_of_q));
+  PS_TRY(upload(p, &p->qmax_d, p->qmax));
+  PS_TRY(compute_counts(p));
+
+  const size_t nc = p->cand.size() / p->order;
+  std::vector<int> ent;
+  std::vector<double> fnorm;
+  const double N3 = (double)p->N * p->N * p->N;
+  double phys = 1.0;
+  if (d.box_length > 0) {
+    const double V = d.box_length * d.box_length * d.box_length;
+    phys = std::pow(V, p->order - 1) / std::pow((double)p->N, 3 * p->order);
+  }
+  std::vector<int> lookup;
+  if (p->order == 3) lookup.assign((size_t)p->nb * p->nb * p->nb, -1);
+  for (size_t c = 0; c < nc; ++c) {
+    if (p->cand_count[c] <= 0) continue;
+    const int k = (int)p->closing.size();
+    p->closing.push_back((int)c);
+    for (int j = 0; j < p->order; ++j) p->cl_bins.push_back(p->cand[c * p->order + j]);
+    p->cl_counts.push_back(p->cand_count[c]);
+    ent.push_back(ent_of_cand[c]);
+    fnorm.push_back(phys / (N3 * (double)p->cand_count[c]));
+    if (p->order == 3) {
+      const int* t = &p->cand[c * 3];
+      lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] = k;
+    }
+  }
+  PS_TRY(upload(p, &p->ent_d, ent));
+  PS_TRY(upload(p, &p->bins_d, p->cl_bins));
+  PS_TRY(upload(p, &p->fnorm_d, fnorm));
+  PS_TRY(dev_alloc(p, &p->flag_d, 256));
+  if (p->order == 3) {
+    PS_TRY(upload(p, &p->lookup_d, lookup));
+    // which (32-pair chunk, 16-shell block) of W can be non-zero
+    const int n_kc = p->n_pairs_padded / 32;
+    std::vector<unsigned char> wmask((size_t)n_kc * ps::kMaxBlkHost, 0);
+    for (int pi = 0; pi < p->n_pairs; ++pi) {
+      const int u = p->pair_uv[pi] & 0xffff, v = p->pair_uv[pi] >> 16;
+      for (int m = 0; m < p->nb; ++m) {
+        int t[3] = {m, u, v};
+        std::sort(t, t + 3);
+        if (lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] >= 0) wmask[(pi / 32) * ps::kMaxBlkHost + m / 16] = 1;
+      }
+    }
+    PS_TRY(upload(p, &p->wmask_d, wmask));
+  }
+  return POLYSPEC_OK;
+}
+
+void release(polyspec_plan_s* p) {
+  DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_tile_d, &p->ent_d,
+                    &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->own_ws};
+  for (DevBuf* b : bufs) dev_free(b);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* polyspec_status_string(polyspec_status st) {
+  switch (st) {
+    case POLYSPEC_OK: return "ok";
+    case POLYSPEC_ERR_INVALID_ARG: return "invalid argument";
+    case POLYSPEC_ERR_ALIASING: return "configuration aliases";
+    case POLYSPEC_ERR_OUT_OF_MEMORY: return "out of memory";
+    case POLYSPEC_ERR_DEVICE: return "device error";
+    case POLYSPEC_ERR_COUNT_NOT_INTEGRAL: return "polygon count not integral";
+    case POLYSPEC_ERR_STATE: return "call out of order";
+    case POLYSPEC_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* polyspec_last_error(polyspec_plan_t plan) {
+  return plan ? plan->last_error.c_str() : g_plan_error.c_str();
+}
+
+polyspec_status polyspec_plan(const polyspec_desc* desc, void* stream, polyspec_plan_t* out) {
+  g_plan_error.clear();
+  if (!desc || !out) {
+    g_plan_error = "null descriptor or output pointer";
+    return POLYSPEC_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  polyspec_plan_s* p = new (std::nothrow) polyspec_plan_s;
+  if (!p) {
+    g_plan_error = "host allocation failed";
+    return POLYSPEC_ERR_OUT_OF_MEMORY;
+  }
+  p->desc = *desc;
+  p->stream = (hipStream_t)stream;
+  polyspec_status st;
+  try {
+    st = build_plan(p);
+  } catch (const std::bad_alloc&) {
+    st = p->fail(POLYSPEC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    st = p->fail(POLYSPEC_ERR_INVALID_ARG, "unexpected failure while building the plan");
+  }
+  if (st != POLYSPEC_OK) {
+    g_plan_error = p->last_error;
+    release(p);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_workspace_size(polyspec_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return POLYSPEC_ERR_INVALID_ARG;
+  *bytes = layout_of(p).total;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_set_workspace(polyspec_plan_t p, void* d_ptr, size_t bytes) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (p->ws) return p->fail(POLYSPEC_ERR_STATE, "workspace already set or allocated");
+  if (!d_ptr || ((uintptr_t)d_ptr & 255)) return p->fail(POLYSPEC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < layout_of(p).total) return p->fail(POLYSPEC_ERR_INVALID_ARG, "workspace too small");
+  p->ws = (char*)d_ptr;
+  p->ws_size = bytes;
+  carve(p, p->ws);
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_set_precision(polyspec_plan_t p, int32_t precision) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (precision < 0 || precision > 2) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown precision");
+  p->prec = precision;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!d_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null input");
+  PS_TRY(ensure_workspace(p));
+  const int nz = p->batch * p->nb;
+  hipStream_t st = p->stream;
+  Geom gin = make_geom(p, 0, 0);
+  if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM) {
+    PS_HIP(p, ps::launch_box_from_half_spectrum((const cplx<float>*)d_delta, p->box, gin, p->batch, st));
+  } else {
+    PS_HIP(p, ps::launch_r2c_q3((const float*)d_delta, p->H2, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
+    PS_HIP(p, ps::launch_r2c_q2(p->H2, p->H1, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
+    PS_HIP(p, ps::launch_r2c_q1<false>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->box,
+                                       (const cplx<float>*)p->tw32.p, gin, p->batch, st));
+  }
+  Geom gs = make_geom(p, p->nb, 1);
+  PS_HIP(p, ps::launch_fill_u32(p->absmax, 0u, (size_t)nz, st));
+  PS_HIP(p, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
+                                            (const cplx<float>*)p->tw32.p, gs, nz, st));
+  PS_HIP(p, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, (const cplx<float>*)p->tw32.p, gs, nz,
+                                     st));
+  PS_HIP(p, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D, p->absmax, (const cplx<float>*)p->tw32.p, gs,
+                              nz, st));
+  p->have_fields = true;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_raw_sums) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
+  if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_contract before polyspec_shells");
+  hipStream_t st = p->stream;
+  ps::CtrParams cp;
+  cp.D = p->D;
+  cp.pair_uv = (const int*)p->pairs_d.p;
+  cp.slots = (const int*)p->slots_d.p;
+  cp.slot_tile = (const int*)p->slot_tile_d.p;
+  cp.absmax = p->absmax;
+  cp.partials = p->partials;
+  cp.G = p->G;
+  cp.n_shells = p->nb;
+  cp.n_blk = p->n_blk;
+  cp.n_pairs_padded = p->n_pairs_padded;
+  cp.n_tiles = p->n_tiles;
+  cp.ksteps = p->ksteps;
+  cp.n_chunks = p->n_chunks;
+  PS_HIP(p, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
+  const long long n_ent = (long long)p->n_tiles * 256;
+  PS_HIP(p, ps::launch_reduce_f32(p->partials, p->red, p->n_chunks, p->red_cpg, p->red_groups, n_ent, p->batch, st));
+  const bool guard = p->desc.flags & POLYSPEC_NAN_GUARD;
+  if (guard) PS_HIP(p, ps::launch_fill_u32(p->flag_d.p, 0u, 1, st));
+  const int ncl = (int)p->closing.size();
+  if (ncl > 0)
+    PS_HIP(p, ps::launch_gather(p->red, p->red_groups, n_ent, (const int*)p->ent_d.p, (const int*)p->bins_d.p,
+                                p->order, (const double*)p->fnorm_d.p, ncl, p->absmax, p->nb, p->prec, d_out,
+                                d_raw_sums, guard ? (int*)p->flag_d.p : nullptr, p->batch, st));
+  if (guard) {
+    int flag = 0;
+    PS_HIP(p, hipMemcpyAsync(&flag, p->flag_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    PS_HIP(p, hipStreamSynchronize(st));
+    if (flag) return p->fail(POLYSPEC_ERR_DEVICE, "non-finite polyspectrum value");
+  }
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, float* d_grad_delta) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (p->order != 3) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward is implemented for order 3");
+  if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM)
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward needs real-space input");
+  if (!d_grad_out || !d_grad_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null pointer");
+  if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_backward before polyspec_shells");
+  hipStream_t st = p->stream;
+  const int nz = p->batch * p->nb;
+  const int ncl = (int)p->closing.size();
+  const int aprec = (p->prec == POLYSPEC_FP32) ? 0 : 1;  // FP16 mode uses the bf16 split here
+  PS_HIP(p, ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p,
+                                       (const int*)p->pairs_d.p, p->n_pairs, p->n_pairs_padded, p->nb, ncl, p->W,
+                                       p->batch, st));
+  PS_HIP(p, ps::launch_adjoint_gemm(aprec, p->D, p->W, (const unsigned char*)p->wmask_d.p, (const int*)p->pairs_d.p,
+                                    p->n_pairs_padded, p->nb, p->n_blk, p->G, p->A, p->batch, st));
+  const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
+  PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
+  Geom gs = make_geom(p, p->nb, 1);
+  const cplx<float>* tw = (const cplx<float>*)p->tw32.p;
+  PS_HIP(p, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
+  PS_HIP(p, ps::launch_r2c_q2(p->H2, p->H1, tw, gs, nz, st));
+  PS_HIP(p, ps::launch_r2c_q1<true>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
+                                    nz, st));
+  Geom gall = make_geom(p, 0, 0);
+  PS_HIP(p, ps::launch_c2r_p1<float, false>(p->gbox, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
+                                            tw, gall, p->batch, st));
+  PS_HIP(p, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, tw, gall, p->batch, st));
+  PS_HIP(p, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, d_grad_delta, nullptr, tw, gall, p->batch, st));
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_tuples(polyspec_plan_t p, int64_t* n_closing, int32_t* h_bins, int64_t* h_counts) {
+  if (!p || !n_closing) return POLYSPEC_ERR_INVALID_ARG;
+  *n_closing = (int64_t)p->closing.size();
+  if (h_bins)
+    for (size_t i = 0; i < p->cl_bins.size(); ++i) h_bins[i] = p->cl_bins[i] + 1;
+  if (h_counts) std::memcpy(h_counts, p->cl_counts.data(), p->cl_counts.size() * sizeof(int64_t));
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_candidates(polyspec_plan_t p, int64_t* n_candidates, int32_t* h_bins, double* h_quotients) {
+  if (!p || !n_candidates) return POLYSPEC_ERR_INVALID_ARG;
+  *n_candidates = (int64_t)(p->cand.size() / p->order);
+  if (h_bins)
+    for (size_t i = 0; i < p->cand.size(); ++i) h_bins[i] = p->cand[i] + 1;
+  if (h_quotients) std::memcpy(h_quotients, p->cand_quot.data(), p->cand_quot.size() * sizeof(double));
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_fields(polyspec_plan_t p, const float** d_fields) {
+  if (!p || !d_fields) return POLYSPEC_ERR_INVALID_ARG;
+  if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "no shell fields yet");
+  *d_fields = p->D;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_destroy(polyspec_plan_t p) {
+  if (!p) return POLYSPEC_OK;
+  (void)hipStreamSynchronize(p->stream);
+  release(p);
+  delete p;
+  return POLYSPEC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+"""GPU parity of the HIP path against the FP64 oracle (small and medium grids).
+
+Tolerances: polygon counts bit-exact; B within 1e-5 relative (L2 over the closing
+tuples) for the FP32 contraction and 1e-4 for the split-precision contractions;
+gradients within 1e-4 relative (L2 over the grid).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ps():
+    import paper_1904_11055_amd as ps
+    return ps
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _run(delta, order, nb, width, precision=0, flags=0, box_length=0.0):
+    import torch
+    ps = _ps()
+    delta = np.asarray(delta, dtype=np.float32)
+    if delta.ndim == 3:
+        delta = delta[None]
+    plan = ps.Plan(delta.shape[-1], order, nb, width, batch=delta.shape[0], precision=precision,
+                   flags=flags, box_length=box_length, device="cuda:0")
+    x = torch.from_numpy(delta).to("cuda:0")
+    plan.shells(x)
+    B, S = plan.contract(raw=True)
+    torch.cuda.synchronize()
+    return plan, B.cpu().numpy(), S.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def bispec64():
+    delta = fieldgen.workload_fields("bispec_64")[0]
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 16, 1.0, return_fields=True)
+    return delta, ref
+
+
+def test_counts_bit_exact_64(gpu, bispec64):
+    delta, ref = bispec64
+    plan, B, _ = _run(delta, 3, 16, 1.0)
+    assert np.array_equal(plan.tuples, ref["tuples"])
+    assert np.array_equal(plan.counts, ref["counts"])
+    gold = np.loadtxt(os.path.join(GOLDEN, "bispec_64_counts.txt"), dtype=np.int64)
+    assert np.array_equal(plan.counts, gold[:, 3])
+    bins, quot = plan.candidates()
+    assert np.abs(quot - np.rint(quot)).max() < 1e-6
+    plan.close()
+
+
+def test_shell_fields_64(gpu, bispec64):
+    delta, ref = bispec64
+    plan, _, _ = _run(delta, 3, 16, 1.0)
+    f = plan.fields().cpu().numpy()[0]
+    d = ref["fields"]
+    scale = np.abs(d).max(axis=(1, 2, 3))
+    err = np.abs(f - d).max(axis=(1, 2, 3)) / scale
+    assert err.max() < 2e-6, err
+    plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-4)])
+def test_bispectrum_64(gpu, bispec64, precision, tol):
+    delta, ref = bispec64
+    plan, B, S = _run(delta, 3, 16, 1.0, precision=precision)
+    assert _rel(B[0], ref["B"]) < tol
+    assert _rel(S[0], ref["sums"]) < tol
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_bispectrum_ragged_shells(gpu, precision):
+    # 20 shells: two shell blocks, the second ragged; 240 pairs over 15 pair blocks
+    delta = fieldgen.lognormal_field(64, 9).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 20, 1.0)
+    plan, B, _ = _run(delta, 3, 20, 1.0, precision=precision)
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(B[0], ref["B"]) < (1e-5 if precision == 0 else 1e-4)
+    plan.close()
+
+
+def test_unit_spectrum_gives_one(gpu):
+    plan, B, _ = _run(fieldgen.unit_spectrum_field(32), 3, 10, 1.0)
+    np.testing.assert_allclose(B[0], 1.0, rtol=2e-6)
+    plan.close()
+
+
+def test_power_spectrum(gpu):
+    delta = fieldgen.gaussian_field(32, 4).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 2, 14, 1.0)
+    plan, B, _ = _run(delta, 2, 14, 1.0)
+    assert np.array_equal(plan.counts, ref["counts"])
+    np.testing.assert_allclose(B[0], ref["B"], rtol=1e-5)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-4)])
+def test_trispectrum(gpu, precision, tol):
+    delta = fieldgen.lognormal_field(32, 6).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 4, 7, 1.0)
+    plan, B, _ = _run(delta, 4, 7, 1.0, precision=precision)
+    assert np.array_equal(plan.tuples, ref["tuples"])
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(B[0], ref["B"]) < tol
+    plan.close()
+
+
+def test_aliased_configuration(gpu):
+    ps = _ps()
+    delta = fieldgen.gaussian_field(32, 12).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 12, 1.0, allow_aliasing=True)
+    plan, B, _ = _run(delta, 3, 12, 1.0, flags=ps.ALLOW_ALIASING)
+    assert np.array_equal(plan.tuples, ref["tuples"])
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(B[0], ref["B"]) < 1e-5
+    plan.close()
+
+
+def test_width_two_shells(gpu):
+    delta = fieldgen.lognormal_field(64, 2).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 9, 2.0)
+    plan, B, _ = _run(delta, 3, 9, 2.0)
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(B[0], ref["B"]) < 1e-5
+    plan.close()
+
+
+def test_half_spectrum_input_and_box_length(gpu):
+    import torch
+    ps = _ps()
+    delta = fieldgen.gaussian_field(32, 14).astype(np.float32)
+    L = 1000.0
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 8, 1.0, box_length=L)
+    hs = np.fft.rfftn(delta.astype(np.float64)).astype(np.complex64)
+    plan = ps.Plan(32, 3, 8, 1.0, flags=ps.INPUT_HALF_SPECTRUM, box_length=L, device="cuda:0")
+    plan.shells(torch.from_numpy(hs)[None].to("cuda:0"))
+    B = plan.contract().cpu().numpy()[0]
+    assert _rel(B, ref["B"]) < 1e-5
+    plan.close()
+
+
+def test_batch_matches_single(gpu):
+    fields = np.stack([fieldgen.gaussian_field(32, s) for s in (21, 22, 23)]).astype(np.float32)
+    plan, B, _ = _run(fields, 3, 8, 1.0)
+    for b in range(3):
+        ref = O.polyspectrum(fields[b].astype(np.float64), 3, 8, 1.0)
+        assert _rel(B[b], ref["B"]) < 1e-5
+    plan.close()
+
+
+def test_reruns_are_bitwise_equal(gpu):
+    import torch
+    delta = fieldgen.gaussian_field(64, 3).astype(np.float32)
+    plan, B1, _ = _run(delta, 3, 16, 1.0, precision=1)
+    B2 = plan.contract().cpu().numpy()
+    plan.shells(torch.from_numpy(delta)[None].to("cuda:0"))
+    B3 = plan.contract().cpu().numpy()
+    assert np.array_equal(B1, B2) and np.array_equal(B1, B3)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-4), (1, 1e-4)])
+def test_gradient_matches_oracle(gpu, precision, tol):
+    import torch
+    ps = _ps()
+    N, nb = 32, 8
+    delta = fieldgen.gaussian_field(N, 31).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 3, nb, 1.0, return_fields=True)
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal(len(ref["B"]))
+    gref = O.gradient(delta.astype(np.float64), 3, nb, 1.0, g, result=ref)
+    plan = ps.Plan(N, 3, nb, 1.0, precision=precision, device="cuda:0")
+    x = torch.from_numpy(delta)[None].to("cuda:0").requires_grad_(True)
+    B = ps.polyspectrum(x, plan)
+    B.backward(torch.from_numpy(g)[None].to("cuda:0"))
+    assert _rel(x.grad.cpu().numpy()[0], gref) < tol
+    plan.close()
+
+
+def test_state_and_guard_errors(gpu):
+    import torch
+    ps = _ps()
+    plan = ps.Plan(32, 3, 8, 1.0, flags=ps.NAN_GUARD, device="cuda:0")
+    with pytest.raises(ps.PolyspecError) as e:
+        plan.contract()
+    assert e.value.status == 6
+    with pytest.raises(ps.PolyspecError) as e:
+        plan.backward(torch.zeros(1, plan.n_closing, dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == 6
+    bad = torch.zeros(1, 32, 32, 32, device="cuda:0")
+    bad[0, 1, 2, 3] = float("nan")
+    plan.shells(bad)
+    with pytest.raises(ps.PolyspecError) as e:
+        plan.contract()
+    assert e.value.status == 4
+    plan.close()
+    p4 = ps.Plan(32, 4, 5, 1.0, device="cuda:0")
+    p4.shells(torch.zeros(1, 32, 32, 32, device="cuda:0"))
+    with pytest.raises(ps.PolyspecError) as e:
+        p4.backward(torch.zeros(1, p4.n_closing, dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == 7
+    p4.close()
