@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Bispectrum forward + backward on one MI355X: 512^3 lognormal field, 64 unit-width shells.
+
+One step = the whole hot path on one field resident in HBM: input transform,
+64 shell fields, the matrix-core product sums with float64 reduction and
+normalisation, and the adjoint back to dL/d delta (loss sum_t B_t^2, so
+dL/dB = 2 B).  Polygon counts are computed once when the plan is built and are
+not part of a step.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bispec_512_lognormal")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=1, help="x0-planes in the oracle's timing sample")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("contract.hip", "fft.hip"):
+        with open(os.path.join(ROOT, "paper_1904_11055_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, precision: str):
+    """HBM bytes per launch of the contraction from committed counter runs, if still current."""
+    path = os.path.join(ROOT, "profiles", f"contract_tiles_{workload}_{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(delta32, w, n_closing, planes: int):
+    """The FP64 oracle timed on a bounded sample of the same workload, scaled to a full step.
+
+    Sample: one full-grid inverse real FFT and one forward real FFT (each needed
+    n_shells + 1 times per step), plus the per-grid-point work (pair products, the
+    product-sum matrix product and the adjoint's weighted pair sum) over `planes`
+    x0-planes of the grid, scaled by N / planes.
+    """
+    import numpy as np
+
+    import oracle as O
+    from oracle.polyspec import irfftn, rfftn
+    N, nb, width = w["N"], w["n_shells"], w["width"]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count() or 1
+    delta = delta32.astype(np.float64)
+    t0 = time.perf_counter()
+    dhat = rfftn(delta)
+    t_r2c = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _ = irfftn(dhat, s=(N, N, N))
+    t_c2r = time.perf_counter() - t0
+    pl = list(range(planes))
+    fields = O.shell_fields_on_planes(dhat, N, nb, width, pl)          # [nb, planes, N, N]
+    tuples = O.candidate_tuples(3, nb, O.is_alias_free(N, 3, nb, width))
+    t0 = time.perf_counter()
+    S = O.product_sums(fields, tuples)
+    t_ctr = time.perf_counter() - t0
+    wts = np.linspace(-1.0, 1.0, len(tuples))
+    t0 = time.perf_counter()
+    W = O.adjoint_weights(tuples, wts, nb)
+    pairs = O.pair_list(nb)
+    flat = fields.reshape(nb, -1)
+    a = np.empty_like(flat)
+    for x0 in range(0, flat.shape[1], 8192):
+        blk = flat[:, x0:x0 + 8192]
+        a[:, x0:x0 + 8192] = W @ (blk[pairs[:, 0] - 1] * blk[pairs[:, 1] - 1])
+    t_adj = time.perf_counter() - t0
+    del S, a
+    scale = N / planes
+    t_step = (nb + 1) * (t_r2c + t_c2r) + scale * (t_ctr + t_adj)
+    G = N ** 3
+    return {
+        "value": n_closing * G / t_step,
+        "unit": "bin-triplets*gridpts/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: one {N}^3 rfftn ({t_r2c:.2f} s) and irfftn ({t_c2r:.2f} s) scaled x{nb + 1} "
+                   f"each; product sums over all {len(tuples)} candidate triplets and the adjoint pair "
+                   f"GEMM on {planes} of {N} x0-planes ({t_ctr:.2f} s + {t_adj:.2f} s) scaled x{scale:g}; "
+                   f"estimated step {t_step:.1f} s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(sharding over x0-slabs is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_1904_11055_amd as ps
+
+    w = fieldgen.WORKLOADS[args.workload]
+    if w["order"] != 3:
+        raise SystemExit("the benchmark step needs an order-3 workload (forward + adjoint)")
+    N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
+    prec = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}[args.precision]
+    dev = torch.device("cuda:0")
+    log(f"generating {args.workload} fields")
+    fields = fieldgen.workload_fields(args.workload, dtype=np.float32)
+    x = torch.from_numpy(fields).to(dev)
+    torch.cuda.synchronize()
+    log("building plan (float64 polygon counts)")
+    t0 = time.perf_counter()
+    plan = ps.Plan(N, 3, nb, width, batch=batch, precision=prec, device=dev)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    log(f"plan built in {plan_s:.2f} s: {plan.n_closing} closing triplets")
+    G = N ** 3
+
+    def step():
+        plan.shells(x)
+        B = plan.contract()
+        return B, plan.backward(2.0 * B)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    ps.polyspec_profile(plan.handle, True)
+    ps.polyspec_profile_read(plan.handle)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B, g = step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    prof = ps.polyspec_profile_read(plan.handle)
+    ms_step = 1000.0 * t / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step")
+
+    def avg(name):
+        ms, n = prof[name]
+        return ms / n if n else 0.0
+
+    fwd = ["input_q3", "input_q2", "input_q1", "shell_p1", "shell_p2", "shell_p3", "contract", "reduce", "gather"]
+    bwd = ["adj_weights", "adj_gemm", "adj_q3", "adj_q2", "adj_q1", "grad_p1", "grad_p2", "grad_p3"]
+    fwd_ms = sum(avg(k) for k in fwd)
+    bwd_ms = sum(avg(k) for k in bwd)
+    ctr_ms = avg("contract")
+    n_pairs = nb * (nb + 1) // 2
+    alg_flops = (2.0 * plan.n_closing + n_pairs) * G * batch
+    achieved = alg_flops / (ctr_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    traffic = load_traffic(args.workload, args.precision)
+    out = {
+        "metric": "bispectrum bin-triplets*gridpts/s at 512^3 (split-MFMA vs FP32); fwd+bwd ms",
+        "value": plan.n_closing * G * batch / (ms_step * 1e-3),
+        "unit": "bin-triplets*gridpts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "order": 3, "n_shells": nb, "shell_width": width,
+                   "batch": batch, "field": w["field"], "seeds": w["seeds"], "n_closing": plan.n_closing,
+                   "precision": args.precision, "parallelism": "none (1 GPU)"},
+        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "plan_s": plan_s,
+        "contract_ms": ctr_ms,
+        "contract_rate": plan.n_closing * G * batch / (ctr_ms * 1e-3),
+        "phase_ms": {k: round(avg(k), 4) for k in ps.PHASES if prof[k][1]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "contract_tiles", "alg_flops_per_launch": alg_flops},
+    }
+    if not args.no_fp32_compare and args.precision != "fp32":
+        plan.precision = ps.FP32
+        plan.contract()
+        ps.polyspec_profile_read(plan.handle)
+        for _ in range(2):
+            plan.contract()
+        p32 = ps.polyspec_profile_read(plan.handle)
+        ms32 = p32["contract"][0] / max(1, p32["contract"][1])
+        out["fp32_contract_ms"] = ms32
+        out["fp32_contract_rate"] = plan.n_closing * G * batch / (ms32 * 1e-3)
+        out["split_speedup_vs_fp32"] = ms32 / ctr_ms
+        plan.precision = prec
+        log(f"fp32 contraction {ms32:.2f} ms vs {args.precision} {ctr_ms:.2f} ms")
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(fields[0], w, plan.n_closing * batch, args.cpu_planes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

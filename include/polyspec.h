@@ -137,6 +137,38 @@ polyspec_status polyspec_candidates(polyspec_plan_t plan, int64_t* n_candidates,
  * for inspection.  POLYSPEC_ERR_STATE before polyspec_shells. */
 polyspec_status polyspec_fields(polyspec_plan_t plan, const float** d_fields);
 
+/* Kernel timing.  Phases of polyspec_shells, polyspec_contract and
+ * polyspec_backward, one kernel each, in launch order. */
+enum {
+  POLYSPEC_PH_INPUT_Q3 = 0,   /* input transform, rows x2 -> q2            */
+  POLYSPEC_PH_INPUT_Q2,       /* input transform, x0 -> q0                  */
+  POLYSPEC_PH_INPUT_Q1,       /* input transform, x1 -> q1 into the ball    */
+  POLYSPEC_PH_SHELL_P1,       /* shell fields, masked q1 -> x1              */
+  POLYSPEC_PH_SHELL_P2,       /* shell fields, q0 -> x0                     */
+  POLYSPEC_PH_SHELL_P3,       /* shell fields, q2 -> x2 complex-to-real     */
+  POLYSPEC_PH_CONTRACT,       /* matrix-core product sums per grid chunk    */
+  POLYSPEC_PH_REDUCE,         /* float64 sum over grid chunks               */
+  POLYSPEC_PH_GATHER,         /* tuple gather and normalisation             */
+  POLYSPEC_PH_ADJ_WEIGHTS,    /* adjoint: weights W[m][pair]                */
+  POLYSPEC_PH_ADJ_GEMM,       /* adjoint: a_m = W (d_u d_v)                 */
+  POLYSPEC_PH_ADJ_Q3,         /* adjoint: rows x2 -> q2                     */
+  POLYSPEC_PH_ADJ_Q2,         /* adjoint: x0 -> q0                          */
+  POLYSPEC_PH_ADJ_Q1,         /* adjoint: x1 -> q1, shell-masked merge      */
+  POLYSPEC_PH_GRAD_P1,        /* gradient field, q1 -> x1                   */
+  POLYSPEC_PH_GRAD_P2,        /* gradient field, q0 -> x0                   */
+  POLYSPEC_PH_GRAD_P3,        /* gradient field, q2 -> x2 complex-to-real   */
+  POLYSPEC_N_PHASES
+};
+
+/* Turns event timing of every kernel launch on (enable != 0) or off.  Timing adds
+ * a pair of HIP events per launch on the plan's stream and nothing else. */
+polyspec_status polyspec_profile(polyspec_plan_t plan, int32_t enable);
+
+/* Waits for the plan's stream, then writes the milliseconds spent in each phase
+ * (h_ms, double [POLYSPEC_N_PHASES]) and the number of timed launches (h_launches,
+ * int64 [POLYSPEC_N_PHASES], may be NULL) since the last read, and resets them. */
+polyspec_status polyspec_profile_read(polyspec_plan_t plan, double* h_ms, int64_t* h_launches);
+
 /* Releases the plan and everything it allocated (not caller workspace).  Waits for
  * the plan's stream.  NULL is accepted. */
 polyspec_status polyspec_destroy(polyspec_plan_t plan);

@@ -24,6 +24,7 @@ __all__ = [
     "polyspec_plan", "polyspec_shells", "polyspec_contract", "polyspec_backward",
     "polyspec_workspace_size", "polyspec_set_workspace", "polyspec_set_precision",
     "polyspec_tuples", "polyspec_candidates", "polyspec_fields", "polyspec_destroy",
+    "polyspec_profile", "polyspec_profile_read", "PHASES",
     "polyspec_status_string", "polyspec_last_error",
 ]
 
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH):
         "polyspec_candidates": (ctypes.c_int, [P, D(ctypes.c_int64), V, V]),
         "polyspec_fields": (ctypes.c_int, [P, D(ctypes.c_void_p)]),
         "polyspec_destroy": (ctypes.c_int, [P]),
+        "polyspec_profile": (ctypes.c_int, [P, ctypes.c_int32]),
+        "polyspec_profile_read": (ctypes.c_int, [P, V, V]),
         "polyspec_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "polyspec_last_error": (ctypes.c_char_p, [P]),
     }
@@ -172,6 +175,25 @@ def polyspec_fields(plan) -> int:
     return ptr.value
 
 
+PHASES = ["input_q3", "input_q2", "input_q1", "shell_p1", "shell_p2", "shell_p3", "contract",
+          "reduce", "gather", "adj_weights", "adj_gemm", "adj_q3", "adj_q2", "adj_q1",
+          "grad_p1", "grad_p2", "grad_p3"]
+
+
+def polyspec_profile(plan, enable: bool):
+    _check(load_library().polyspec_profile(plan, 1 if enable else 0), "polyspec_profile", plan)
+
+
+def polyspec_profile_read(plan):
+    """{phase: (milliseconds, launches)} since the last read (synchronises the stream)."""
+    ms = np.zeros(len(PHASES), dtype=np.float64)
+    calls = np.zeros(len(PHASES), dtype=np.int64)
+    _check(load_library().polyspec_profile_read(plan, ms.ctypes.data_as(ctypes.c_void_p),
+                                                calls.ctypes.data_as(ctypes.c_void_p)),
+           "polyspec_profile_read", plan)
+    return {name: (float(ms[i]), int(calls[i])) for i, name in enumerate(PHASES)}
+
+
 def polyspec_destroy(plan):
     _check(load_library().polyspec_destroy(plan), "polyspec_destroy")
 
@@ -260,7 +282,7 @@ class _DeviceArray:
 
     def __init__(self, ptr, shape, typestr):
         self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
-                                         "data": (int(ptr), True), "version": 2}
+                                         "data": (int(ptr), False), "version": 2}
 
 
 def polyspectrum(delta, plan: Plan):

@@ -110,6 +110,13 @@ struct polyspec_plan_s {
   float* W = nullptr;
   bool have_fields = false;
 
+  // per-kernel timing with HIP events on the plan's stream
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double prof_ms[POLYSPEC_N_PHASES] = {};
+  int64_t prof_calls[POLYSPEC_N_PHASES] = {};
+
   polyspec_status fail(polyspec_status st, const std::string& msg) {
     last_error = msg;
     return st;
@@ -162,6 +169,36 @@ polyspec_status upload(polyspec_plan_s* p, DevBuf* b, const std::vector<T>& v) {
   do {                                   \
     polyspec_status s_ = (expr);         \
     if (s_ != POLYSPEC_OK) return s_;    \
+  } while (0)
+
+hipEvent_t ev_get(polyspec_plan_s* p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Launch with optional start/stop events around it (phase ph).
+#define PS_TIMED(p, ph, ...)                                                  \
+  do {                                                                        \
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;                                  \
+    if ((p)->prof) {                                                          \
+      e0_ = ev_get(p);                                                        \
+      e1_ = ev_get(p);                                                        \
+      if (e0_ && e1_) PS_HIP(p, hipEventRecord(e0_, (p)->stream));            \
+    }                                                                         \
+    PS_HIP(p, __VA_ARGS__);                                                   \
+    if ((p)->prof && e0_ && e1_) {                                            \
+      PS_HIP(p, hipEventRecord(e1_, (p)->stream));                            \
+      (p)->ev_pending.push_back({(ph), {e0_, e1_}});                          \
+    }                                                                         \
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -631,6 +668,13 @@ polyspec_status build_plan(polyspec_plan_s* p) {
 }
 
 void release(polyspec_plan_s* p) {
+  for (auto& pe : p->ev_pending) {
+    p->ev_pool.push_back(pe.second.first);
+    p->ev_pool.push_back(pe.second.second);
+  }
+  p->ev_pending.clear();
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  p->ev_pool.clear();
   DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_tile_d, &p->ent_d,
                     &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->own_ws};
   for (DevBuf* b : bufs) dev_free(b);
@@ -727,18 +771,18 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM) {
     PS_HIP(p, ps::launch_box_from_half_spectrum((const cplx<float>*)d_delta, p->box, gin, p->batch, st));
   } else {
-    PS_HIP(p, ps::launch_r2c_q3((const float*)d_delta, p->H2, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
-    PS_HIP(p, ps::launch_r2c_q2(p->H2, p->H1, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
-    PS_HIP(p, ps::launch_r2c_q1<false>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->box,
+    PS_TIMED(p, POLYSPEC_PH_INPUT_Q3, ps::launch_r2c_q3((const float*)d_delta, p->H2, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
+    PS_TIMED(p, POLYSPEC_PH_INPUT_Q2, ps::launch_r2c_q2(p->H2, p->H1, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
+    PS_TIMED(p, POLYSPEC_PH_INPUT_Q1, ps::launch_r2c_q1<false>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->box,
                                        (const cplx<float>*)p->tw32.p, gin, p->batch, st));
   }
   Geom gs = make_geom(p, p->nb, 1);
   PS_HIP(p, ps::launch_fill_u32(p->absmax, 0u, (size_t)nz, st));
-  PS_HIP(p, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
+  PS_TIMED(p, POLYSPEC_PH_SHELL_P1, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
                                             (const cplx<float>*)p->tw32.p, gs, nz, st));
-  PS_HIP(p, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, (const cplx<float>*)p->tw32.p, gs, nz,
+  PS_TIMED(p, POLYSPEC_PH_SHELL_P2, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, (const cplx<float>*)p->tw32.p, gs, nz,
                                      st));
-  PS_HIP(p, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D, p->absmax, (const cplx<float>*)p->tw32.p, gs,
+  PS_TIMED(p, POLYSPEC_PH_SHELL_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D, p->absmax, (const cplx<float>*)p->tw32.p, gs,
                               nz, st));
   p->have_fields = true;
   return POLYSPEC_OK;
@@ -763,14 +807,14 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   cp.n_tiles = p->n_tiles;
   cp.ksteps = p->ksteps;
   cp.n_chunks = p->n_chunks;
-  PS_HIP(p, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
   const long long n_ent = (long long)p->n_tiles * 256;
-  PS_HIP(p, ps::launch_reduce_f32(p->partials, p->red, p->n_chunks, p->red_cpg, p->red_groups, n_ent, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_REDUCE, ps::launch_reduce_f32(p->partials, p->red, p->n_chunks, p->red_cpg, p->red_groups, n_ent, p->batch, st));
   const bool guard = p->desc.flags & POLYSPEC_NAN_GUARD;
   if (guard) PS_HIP(p, ps::launch_fill_u32(p->flag_d.p, 0u, 1, st));
   const int ncl = (int)p->closing.size();
   if (ncl > 0)
-    PS_HIP(p, ps::launch_gather(p->red, p->red_groups, n_ent, (const int*)p->ent_d.p, (const int*)p->bins_d.p,
+    PS_TIMED(p, POLYSPEC_PH_GATHER, ps::launch_gather(p->red, p->red_groups, n_ent, (const int*)p->ent_d.p, (const int*)p->bins_d.p,
                                 p->order, (const double*)p->fnorm_d.p, ncl, p->absmax, p->nb, p->prec, d_out,
                                 d_raw_sums, guard ? (int*)p->flag_d.p : nullptr, p->batch, st));
   if (guard) {
@@ -793,24 +837,24 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
   const int nz = p->batch * p->nb;
   const int ncl = (int)p->closing.size();
   const int aprec = (p->prec == POLYSPEC_FP32) ? 0 : 1;  // FP16 mode uses the bf16 split here
-  PS_HIP(p, ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p,
+  PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS, ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p,
                                        (const int*)p->pairs_d.p, p->n_pairs, p->n_pairs_padded, p->nb, ncl, p->W,
                                        p->batch, st));
-  PS_HIP(p, ps::launch_adjoint_gemm(aprec, p->D, p->W, (const unsigned char*)p->wmask_d.p, (const int*)p->pairs_d.p,
+  PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM, ps::launch_adjoint_gemm(aprec, p->D, p->W, (const unsigned char*)p->wmask_d.p, (const int*)p->pairs_d.p,
                                     p->n_pairs_padded, p->nb, p->n_blk, p->G, p->A, p->batch, st));
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
   Geom gs = make_geom(p, p->nb, 1);
   const cplx<float>* tw = (const cplx<float>*)p->tw32.p;
-  PS_HIP(p, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
-  PS_HIP(p, ps::launch_r2c_q2(p->H2, p->H1, tw, gs, nz, st));
-  PS_HIP(p, ps::launch_r2c_q1<true>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
+  PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
+  PS_TIMED(p, POLYSPEC_PH_ADJ_Q2, ps::launch_r2c_q2(p->H2, p->H1, tw, gs, nz, st));
+  PS_TIMED(p, POLYSPEC_PH_ADJ_Q1, ps::launch_r2c_q1<true>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
                                     nz, st));
   Geom gall = make_geom(p, 0, 0);
-  PS_HIP(p, ps::launch_c2r_p1<float, false>(p->gbox, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
+  PS_TIMED(p, POLYSPEC_PH_GRAD_P1, ps::launch_c2r_p1<float, false>(p->gbox, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
                                             tw, gall, p->batch, st));
-  PS_HIP(p, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, tw, gall, p->batch, st));
-  PS_HIP(p, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, d_grad_delta, nullptr, tw, gall, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_GRAD_P2, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, tw, gall, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_GRAD_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, d_grad_delta, nullptr, tw, gall, p->batch, st));
   return POLYSPEC_OK;
 }
 
@@ -836,6 +880,33 @@ polyspec_status polyspec_fields(polyspec_plan_t p, const float** d_fields) {
   if (!p || !d_fields) return POLYSPEC_ERR_INVALID_ARG;
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "no shell fields yet");
   *d_fields = p->D;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_profile(polyspec_plan_t p, int32_t enable) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  p->prof = enable != 0;
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_profile_read(polyspec_plan_t p, double* h_ms, int64_t* h_launches) {
+  if (!p || !h_ms) return POLYSPEC_ERR_INVALID_ARG;
+  PS_HIP(p, hipStreamSynchronize(p->stream));
+  for (auto& pe : p->ev_pending) {
+    float ms = 0.f;
+    PS_HIP(p, hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+    p->prof_ms[pe.first] += ms;
+    p->prof_calls[pe.first] += 1;
+    p->ev_pool.push_back(pe.second.first);
+    p->ev_pool.push_back(pe.second.second);
+  }
+  p->ev_pending.clear();
+  for (int i = 0; i < POLYSPEC_N_PHASES; ++i) {
+    h_ms[i] = p->prof_ms[i];
+    if (h_launches) h_launches[i] = p->prof_calls[i];
+    p->prof_ms[i] = 0.0;
+    p->prof_calls[i] = 0;
+  }
   return POLYSPEC_OK;
 }
 

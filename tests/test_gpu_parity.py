@@ -93,7 +93,7 @@ def test_bispectrum_ragged_shells(gpu, precision):
 
 def test_unit_spectrum_gives_one(gpu):
     plan, B, _ = _run(fieldgen.unit_spectrum_field(32), 3, 10, 1.0)
-    np.testing.assert_allclose(B[0], 1.0, rtol=2e-6)
+    np.testing.assert_allclose(B[0], 1.0, rtol=1e-5)   # the FP32 gate
     plan.close()
 
 
