@@ -55,7 +55,7 @@ typedef enum {
  * sums across grid tiles are always float64.  SPLIT_* carry each float32 operand as
  * hi + lo of a 16-bit type and form hi*hi + hi*lo + lo*hi on the matrix cores,
  * accumulating in float32.  SPLIT_FP16 scales every shell by a power of two so that
- * its largest magnitude sits near 2^14; the scale is removed exactly in float64.
+ * its largest magnitude lies in [2^6, 2^7); the scale is removed exactly in float64.
  * (Not in the paper: a precision extension of its product-and-sum step.) */
 typedef enum {
   POLYSPEC_FP32 = 0,

@@ -30,14 +30,15 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 enum { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
-constexpr int kCtrWaves = 8;
+constexpr int kCtrWaves = 16;
 constexpr int kCtrThreads = 64 * kCtrWaves;
-constexpr int kSlots = 32;       // tiles per wave
-constexpr int kKStep = 32;       // grid points per LDS stage
-constexpr int kRowStride = 36;   // floats per staged field row (32 + 4 pad)
+constexpr int kSlots = 14;       // tiles per wave (order 3)
+constexpr int kSlots4 = 12;      // tiles per wave (order 4: B rows formed too)
+constexpr int kSlotsMax = 16;    // stride of the per-wave slot tables
+constexpr int kKStep = 64;       // grid points per LDS stage (two MFMA K-steps)
+constexpr int kRowStride = 68;   // floats per staged field row (64 + 4 pad)
 constexpr int kMaxBlk = 4;       // shell blocks of 16 (n_shells <= 64)
-constexpr int kFp16Top = 14;     // |scaled shell value| < 2^15
-constexpr int kPairShift = 15;   // pair products are scaled down by 2^15 in FP16 mode
+constexpr int kFp16Top = 6;      // |scaled shell value| < 2^7, so pair products stay below 2^14
 
 template <int PREC>
 struct Operand;
@@ -105,15 +106,6 @@ __device__ __forceinline__ void load_row8(const float* lds_row, int g, float (&x
   x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
 }
 
-// Slot word: bits 0..11 A block, 12..23 B block, bit 24 "form A" (A block differs
-// from the previous valid slot's), bit 31 set = empty slot.
-struct SlotWord {
-  int w;
-  __device__ __forceinline__ bool empty() const { return w < 0; }
-  __device__ __forceinline__ int ablk() const { return w & 0xfff; }
-  __device__ __forceinline__ int bblk() const { return (w >> 12) & 0xfff; }
-  __device__ __forceinline__ bool form() const { return (w >> 24) & 1; }
-};
 
 
 __device__ __forceinline__ int fp16_shell_exp(const unsigned* absmax, int idx) {
@@ -122,147 +114,204 @@ __device__ __forceinline__ int fp16_shell_exp(const unsigned* absmax, int idx) {
   return kFp16Top - ilogbf(m);
 }
 
+// Operands in LDS: for each 16-row block, lane l's eight values (rows l % 16,
+// points 8 (l / 16) .. +7) as two 16-byte halves -- hi / lo for the split
+// precisions, values 0..3 / 4..7 for float32 -- stored in separate arrays so
+// consecutive lanes read consecutive 16-byte words.
+template <int PREC>
+__device__ __forceinline__ Operand<PREC> op_from_words(uint4 h, uint4 l) {
+  Operand<PREC> o;
+  if constexpr (PREC == kFP32) {
+    o.v[0] = __uint_as_float(h.x); o.v[1] = __uint_as_float(h.y);
+    o.v[2] = __uint_as_float(h.z); o.v[3] = __uint_as_float(h.w);
+    o.v[4] = __uint_as_float(l.x); o.v[5] = __uint_as_float(l.y);
+    o.v[6] = __uint_as_float(l.z); o.v[7] = __uint_as_float(l.w);
+  } else if constexpr (PREC == kBF16) {
+    o.hi = __builtin_bit_cast(bf16x8, h);
+    o.lo = __builtin_bit_cast(bf16x8, l);
+  } else {
+    o.hi = __builtin_bit_cast(f16x8, h);
+    o.lo = __builtin_bit_cast(f16x8, l);
+  }
+  return o;
+}
+
+// Split four consecutive values of one operand lane into 8-byte hi and lo words.
+template <int PREC>
+__device__ __forceinline__ void split4(float4 v, float scale, uint2& hi, uint2& lo) {
+  if constexpr (PREC == kBF16) {
+    const unsigned b0 = __float_as_uint(v.x), b1 = __float_as_uint(v.y);
+    const unsigned b2 = __float_as_uint(v.z), b3 = __float_as_uint(v.w);
+    hi.x = (b0 >> 16) | (b1 & 0xffff0000u);
+    hi.y = (b2 >> 16) | (b3 & 0xffff0000u);
+    const __bf16 l0 = (__bf16)(v.x - __uint_as_float(b0 & 0xffff0000u));
+    const __bf16 l1 = (__bf16)(v.y - __uint_as_float(b1 & 0xffff0000u));
+    const __bf16 l2 = (__bf16)(v.z - __uint_as_float(b2 & 0xffff0000u));
+    const __bf16 l3 = (__bf16)(v.w - __uint_as_float(b3 & 0xffff0000u));
+    lo.x = (unsigned)__builtin_bit_cast(unsigned short, l0) | ((unsigned)__builtin_bit_cast(unsigned short, l1) << 16);
+    lo.y = (unsigned)__builtin_bit_cast(unsigned short, l2) | ((unsigned)__builtin_bit_cast(unsigned short, l3) << 16);
+  } else {
+    const float y[4] = {v.x * scale, v.y * scale, v.z * scale, v.w * scale};
+    unsigned short hs[4], ls[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const _Float16 h = (_Float16)y[r];
+      hs[r] = __builtin_bit_cast(unsigned short, h);
+      ls[r] = __builtin_bit_cast(unsigned short, (_Float16)(y[r] - (float)h));
+    }
+    hi.x = hs[0] | ((unsigned)hs[1] << 16);
+    hi.y = hs[2] | ((unsigned)hs[3] << 16);
+    lo.x = ls[0] | ((unsigned)ls[1] << 16);
+    lo.y = ls[2] | ((unsigned)ls[3] << 16);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ Operand<PREC> form_pair(const float* S, int uv, int g) {
+  const int u = uv & 0xff, v = (uv >> 8) & 0xff;
+  float x[8], y[8];
+  load_row8(S + u * kRowStride, g, x);
+  load_row8(S + v * kRowStride, g, y);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) x[r] *= y[r];
+  return make_operand<PREC>(x, 1.f);
+}
+
 // ORDER 2: A = shell block, B = shell block;  ORDER 3: A = pair block, B = shell
 // block;  ORDER 4: A = pair block, B = pair block.
+//
+// A stage holds 64 grid points (two MFMA K-steps of 32).  16 waves share one stage;
+// each wave owns up to kSlotsFor<ORDER> tiles.
+template <int ORDER>
+constexpr int slots_for() { return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : kSlots4; }
+
 template <int PREC, int ORDER>
 __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
   __shared__ __attribute__((aligned(16))) float stage[2][(kMaxBlk * 16 + 1) * kRowStride];
-  __shared__ int lds_pairs[2080 + 16];
+  __shared__ uint4 opHi[2][2][kMaxBlk][64];   // [buffer][K-step][shell block][lane]
+  __shared__ uint4 opLo[2][2][kMaxBlk][64];
   __shared__ float lds_scale[kMaxBlk * 16 + 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4;   // which 8-point group of the stage
+  const int g = lane >> 4;   // which 8-point group of a K-step
   const int row = lane & 15;
   const int chunk = blockIdx.x;
   const int group = blockIdx.y;
   const int b = blockIdx.z;
-  const int nrows = p.n_blk * 16;   // staged shell rows (zero beyond n_shells)
-  const int zrow = nrows;           // all-zero row used by padded pairs
+  const int nrows = p.n_blk * 16;   // staged shell rows (zero beyond n_shells); row nrows is all zero
 
-  if (ORDER >= 3) {
-    for (int i = tid; i < p.n_pairs_padded; i += kCtrThreads) lds_pairs[i] = p.pair_uv[i];
+  for (int i = tid; i <= nrows; i += kCtrThreads) {
+    float sc = 1.f;
+    if (PREC == kFP16) sc = i < p.n_shells ? ldexpf(1.0f, fp16_shell_exp(p.absmax, b * p.n_shells + i)) : 0.f;
+    lds_scale[i] = sc;
   }
-  if (PREC == kFP16) {
-    for (int i = tid; i <= nrows; i += kCtrThreads) {
-      float sc = 0.f;
-      if (i < p.n_shells) sc = ldexpf(1.0f, fp16_shell_exp(p.absmax, b * p.n_shells + i));
-      lds_scale[i] = sc;
-    }
-  }
-  // zero rows (padding shells and the zero row) of both stage buffers
   for (int i = tid; i < 2 * (nrows + 1) * kRowStride; i += kCtrThreads) {
     const int buf = i / ((nrows + 1) * kRowStride);
     const int rr = (i / kRowStride) % (nrows + 1);
     if (rr >= p.n_shells) stage[buf][i % ((nrows + 1) * kRowStride)] = 0.f;
   }
+  for (int i = tid; i < 4 * kMaxBlk * 64; i += kCtrThreads) {
+    const int bh = i / (kMaxBlk * 64), kb = (i / 64) % kMaxBlk, ln = i % 64;
+    if (kb * 16 + (ln & 15) >= p.n_shells) {
+      opHi[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
+      opLo[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
+    }
+  }
 
-  SlotWord sw[kSlots];
-  const int* my_slots = p.slots + ((size_t)group * kCtrWaves + wave) * kSlots;
+  constexpr int NS = slots_for<ORDER>();
+  f32x4 acc[NS];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) sw[s].w = __builtin_amdgcn_readfirstlane(my_slots[s]);
+  for (int s = 0; s < NS; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  f32x4 acc[kSlots];
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  // global -> LDS staging: thread t moves float4 #t of the (n_shells x 32) slice
+  // global -> LDS staging: thread t moves float4 #t of the (n_shells x 64) slice and
+  // also writes it, split, into the operand arrays of its shell block and K-step
   const float* Db = p.D + (size_t)b * p.n_shells * p.G;
   const long long x_base = (long long)chunk * p.ksteps * kKStep;
-  const int st_row = tid >> 3, st_col = (tid & 7) * 4;
+  const int st_row = tid >> 4, st_col = (tid & 15) * 4;
   const bool st_active = st_row < p.n_shells;
+  const int st_kb = st_row >> 4;
+  const int st_h = st_col >> 5;                                  // K-step of the stage
+  const int st_lane = (((st_col & 31) >> 3) << 4) | (st_row & 15);
+  const int st_half = (st_col >> 2) & 1;
+  auto stage_store = [&](int buf, float4 v) {
+    if (PREC == kFP16) {  // every FP16 operand works on the power-of-two scaled values
+      const float sc = lds_scale[st_row];
+      v = make_float4(v.x * sc, v.y * sc, v.z * sc, v.w * sc);
+    }
+    *reinterpret_cast<float4*>(&stage[buf][st_row * kRowStride + st_col]) = v;
+    if constexpr (PREC == kFP32) {
+      const uint4 w = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                                 __float_as_uint(v.w));
+      if (st_half) opLo[buf][st_h][st_kb][st_lane] = w; else opHi[buf][st_h][st_kb][st_lane] = w;
+    } else {
+      uint2 hi, lo;
+      split4<PREC>(v, 1.f, hi, lo);
+      reinterpret_cast<uint2*>(&opHi[buf][st_h][st_kb][st_lane])[st_half] = hi;
+      reinterpret_cast<uint2*>(&opLo[buf][st_h][st_kb][st_lane])[st_half] = lo;
+    }
+  };
   float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
   if (st_active) pre = *reinterpret_cast<const float4*>(Db + (size_t)st_row * p.G + x_base + st_col);
   __syncthreads();
-  if (st_active) *reinterpret_cast<float4*>(&stage[0][st_row * kRowStride + st_col]) = pre;
+  if (st_active) stage_store(0, pre);
   __syncthreads();
 
+  // Slot state for the whole chunk.  Uniform byte per slot (4 slots per word, in
+  // SGPRs): bits 0-1 B shell block, 2-3 A shell block (order 2), 4 = form A here,
+  // 7 = empty.  Per-lane shells of the lane's pair rows: order 3 packs (u, v) of
+  // two slots per word, order 4 packs (u_A, v_A, u_B, v_B) of one slot per word.
+  constexpr int NLW = ORDER == 4 ? NS : (NS + 1) / 2;
+  const int* uni = p.slot_uni + ((size_t)group * kCtrWaves + wave) * (kSlotsMax / 4);
+  int un[(NS + 3) / 4];
+#pragma unroll
+  for (int i = 0; i < (NS + 3) / 4; ++i) un[i] = __builtin_amdgcn_readfirstlane(uni[i]);
+  int lv[NLW];
+  if (ORDER >= 3) {
+    const int* lw = p.slot_lane + (((size_t)group * kCtrWaves + wave) * 16 + row) * kSlotsMax;
+#pragma unroll
+    for (int i = 0; i < NLW; ++i) lv[i] = lw[i];
+  }
   for (int ks = 0; ks < p.ksteps; ++ks) {
     const int cur = ks & 1;
     if (ks + 1 < p.ksteps && st_active)
       pre = *reinterpret_cast<const float4*>(Db + (size_t)st_row * p.G + x_base + (ks + 1) * kKStep + st_col);
     const float* S = stage[cur];
-
-    // shell-block operands used as B (ORDER 2, 3) or A (ORDER 2)
-    Operand<PREC> sb[kMaxBlk];
-    if (ORDER <= 3) {
 #pragma unroll
-      for (int kb = 0; kb < kMaxBlk; ++kb) {
-        if (kb < p.n_blk) {
-          float x[8];
-          load_row8(S + (kb * 16 + row) * kRowStride, g, x);
-          sb[kb] = make_operand<PREC>(x, PREC == kFP16 ? lds_scale[kb * 16 + row] : 1.f);
+    for (int h = 0; h < 2; ++h) {
+      Operand<PREC> A;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int info = (un[s / 4] >> (8 * (s % 4))) & 0xff;
+        if (info & 0x80) break;
+        if (ORDER == 2) {
+          const int ab = (info >> 2) & 3;
+          A = op_from_words<PREC>(opHi[cur][h][ab][lane], opLo[cur][h][ab][lane]);
+        } else if (info & 0x10) {
+          const int uv = ORDER == 3 ? (lv[s / 2] >> (16 * (s % 2))) & 0xffff : lv[s] & 0xffff;
+          A = form_pair<PREC>(S + 32 * h, uv, g);
         }
+        Operand<PREC> Bop;
+        if (ORDER == 4) {
+          Bop = form_pair<PREC>(S + 32 * h, (lv[s] >> 16) & 0xffff, g);
+        } else {
+          const int bb = info & 3;
+          Bop = op_from_words<PREC>(opHi[cur][h][bb][lane], opLo[cur][h][bb][lane]);
+        }
+        mma<PREC>(acc[s], A, Bop);
       }
     }
-
-    Operand<PREC> A;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      if (sw[s].empty()) continue;
-      if (ORDER == 2) {
-        const int ab = sw[s].ablk(), bb = sw[s].bblk();
-        Operand<PREC> a2, b2;
-        switch (ab) {
-          case 0: a2 = sb[0]; break;
-          case 1: a2 = sb[1]; break;
-          case 2: a2 = sb[2]; break;
-          default: a2 = sb[3]; break;
-        }
-        switch (bb) {
-          case 0: b2 = sb[0]; break;
-          case 1: b2 = sb[1]; break;
-          case 2: b2 = sb[2]; break;
-          default: b2 = sb[3]; break;
-        }
-        mma<PREC>(acc[s], a2, b2);
-        continue;
-      }
-      if (sw[s].form()) {
-        const int uv = lds_pairs[sw[s].ablk() * 16 + row];
-        const int u = uv & 0xffff, v = uv >> 16;
-        float x[8], y[8];
-        load_row8(S + u * kRowStride, g, x);
-        load_row8(S + v * kRowStride, g, y);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) x[r] *= y[r];
-        float sc = 1.f;
-        if (PREC == kFP16) sc = lds_scale[u] * lds_scale[v] * (1.0f / (float)(1 << kPairShift));
-        A = make_operand<PREC>(x, sc);
-      }
-      if (ORDER == 3) {
-        switch (sw[s].bblk()) {
-          case 0: mma<PREC>(acc[s], A, sb[0]); break;
-          case 1: mma<PREC>(acc[s], A, sb[1]); break;
-          case 2: mma<PREC>(acc[s], A, sb[2]); break;
-          default: mma<PREC>(acc[s], A, sb[3]); break;
-        }
-      } else {  // ORDER 4: B is a pair block too
-        const int uv = lds_pairs[sw[s].bblk() * 16 + row];
-        const int u = uv & 0xffff, v = uv >> 16;
-        float x[8], y[8];
-        load_row8(S + u * kRowStride, g, x);
-        load_row8(S + v * kRowStride, g, y);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) x[r] *= y[r];
-        float sc = 1.f;
-        if (PREC == kFP16) sc = lds_scale[u] * lds_scale[v] * (1.0f / (float)(1 << kPairShift));
-        const Operand<PREC> Bp = make_operand<PREC>(x, sc);
-        mma<PREC>(acc[s], A, Bp);
-      }
-    }
-    if (ks + 1 < p.ksteps && st_active)
-      *reinterpret_cast<float4*>(&stage[cur ^ 1][st_row * kRowStride + st_col]) = pre;
+    if (ks + 1 < p.ksteps && st_active) stage_store(cur ^ 1, pre);
     __syncthreads();
   }
 
   // dump accumulators: tile t, lane l, register r -> partials[..][t][4 l + r]
-  const int* my_tiles = p.slot_tile + ((size_t)group * kCtrWaves + wave) * kSlots;
+  const int* my_tiles = p.slot_tile + ((size_t)group * kCtrWaves + wave) * kSlotsMax;
   float* out = p.partials + ((size_t)b * p.n_chunks + chunk) * (size_t)p.n_tiles * 256;
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    if (sw[s].empty()) continue;
+  for (int s = 0; s < NS; ++s) {
+    if ((un[s / 4] >> (8 * (s % 4))) & 0x80) break;
     const int t = my_tiles[s];
     *reinterpret_cast<f32x4*>(out + (size_t)t * 256 + 4 * lane) = acc[s];
   }
@@ -315,8 +364,6 @@ __global__ void gather_normalize(const double* __restrict__ tmp, int n_groups, l
   if (prec == kFP16) {
     int ex = 0;
     for (int j = 0; j < order; ++j) ex += fp16_shell_exp(absmax, b * n_shells + bins[t * order + j]);
-    if (order == 3) ex -= kPairShift;
-    if (order == 4) ex -= 2 * kPairShift;
     s = ldexp(s, -ex);
   }
   const double B = s * fnorm[t];
@@ -390,21 +437,30 @@ __global__ __launch_bounds__(kCntThreads) void counts_wedge(const double* __rest
 // ---------------------------------------------------------------------------
 // Adjoint (order 3).  W[b][m][pair] = mult * dL/dB_t * fnorm_t with t = sort(m, u, v)
 // and mult the number of times m occurs in t; then a_m[x] = sum_pairs W[m][pair]
-// (d_u d_v)[x] on the matrix cores.
+// (d_u d_v)[x] on the matrix cores with v_mfma_f32_32x32x16 (32 shells m x 32 grid
+// points per tile, 16 pairs per step).  W is written straight into operand order:
+// for pair chunk kc (16 pairs) and shell block mb (32 shells), lane l holds row
+// m = 32 mb + l % 32 and pairs 16 kc + 8 (l / 32) + r, r = 0..7, as two 16-byte
+// words (hi / lo, or values 0..3 / 4..7 in float32).
 // ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+constexpr int kAdjMaxMb = 2;   // shell blocks of 32 (n_shells <= 64)
+
+// W in operand order for the v-major adjoint below: for each v, shell chunk uc of u
+// (16 shells) and shell block mb of m (32 shells), lane l holds W[m][(u, v)] for
+// m = 32 mb + l % 32 and u = 16 uc + 8 (l / 32) + r (r = 0..7; zero when u > v),
+// as two 16-byte words (hi / lo bf16, or values 0..3 / 4..7 in float32).
+// Layout [b][v][uc][mb][hi, lo][lane].
 __global__ void adjoint_weights(const double* __restrict__ grad, const double* __restrict__ fnorm,
-                                const int* __restrict__ lookup /*[nb^3] closing index or -1*/,
-                                const int* __restrict__ pair_uv, int n_pairs, int n_pairs_padded,
-                                int n_shells, int n_closing, float* __restrict__ W) {
-  const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = blockIdx.y;
+                                const int* __restrict__ lookup /*[nb^3] closing index or -1*/, int n_shells,
+                                int n_closing, int prec, uint4* __restrict__ W) {
+  const int m = threadIdx.x;            // 0..63
+  const int u = blockIdx.x;             // 0..63
+  const int v = blockIdx.y;             // 0..n_shells-1
   const int b = blockIdx.z;
-  if (pidx >= n_pairs_padded) return;
   float w = 0.f;
-  if (pidx < n_pairs) {
-    const int uv = pair_uv[pidx];
-    int t0 = m, t1 = uv & 0xffff, t2 = uv >> 16;
-    // sort three values
+  if (m < n_shells && u < n_shells && u <= v) {
+    int t0 = m, t1 = u, t2 = v;
     if (t0 > t1) { int tmp = t0; t0 = t1; t1 = tmp; }
     if (t1 > t2) { int tmp = t1; t1 = t2; t2 = tmp; }
     if (t0 > t1) { int tmp = t0; t0 = t1; t1 = tmp; }
@@ -414,80 +470,172 @@ __global__ void adjoint_weights(const double* __restrict__ grad, const double* _
       w = (float)((double)mult * grad[(size_t)b * n_closing + id] * fnorm[id]);
     }
   }
-  W[((size_t)b * n_shells + m) * n_pairs_padded + pidx] = w;
+  const int uc = u >> 4, q = u & 15, hh = q >> 3, r = q & 7;
+  const int lane = 32 * hh + (m & 31), mb = m >> 5;
+  uint4* base = W + ((((size_t)b * n_shells + v) * 4 + uc) * kAdjMaxMb + mb) * 2 * 64;
+  if (prec == kFP32) {
+    float* dst = reinterpret_cast<float*>(&base[(r < 4 ? 0 : 64) + lane]);
+    dst[r & 3] = w;
+  } else {
+    const unsigned bits = __float_as_uint(w);
+    const float h = __uint_as_float(bits & 0xffff0000u);
+    reinterpret_cast<unsigned short*>(&base[lane])[r] = (unsigned short)(bits >> 16);
+    reinterpret_cast<unsigned short*>(&base[64 + lane])[r] = __builtin_bit_cast(unsigned short, (__bf16)(w - h));
+  }
 }
 
-// a[b][m][x]: one workgroup = 8 waves = 128 grid points (each wave 16 points) and
-// all shells m (blocks of 16).  Reduction over pairs in chunks of 32.
-constexpr int kAdjWaves = 8;
-constexpr int kAdjPts = 16 * kAdjWaves;
-constexpr int kAdjStride = kAdjPts + 4;
+template <int PREC>
+__device__ __forceinline__ void mma32(f32x16& acc, const Operand<PREC>& a, const Operand<PREC>& b) {
+  if constexpr (PREC == kFP32) {
+    // 32x32x2 float32: eight steps; lane l holds K index l / 32 of each
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[r], b.v[r], acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo, b.hi, acc, 0, 0, 0);
+  }
+}
+
+// As mma32, into a fresh accumulator (C = 0).
+template <int PREC>
+__device__ __forceinline__ void mma32_first(f32x16& acc, const Operand<PREC>& a, const Operand<PREC>& b) {
+  const f32x16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if constexpr (PREC == kFP32) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[0], b.v[0], z, 0, 0, 0);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[r], b.v[r], acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.hi, z, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo, b.hi, acc, 0, 0, 0);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ float operand_value(const Operand<PREC>& o, int r) {
+  if constexpr (PREC == kFP32) return o.v[r];
+  else return (float)o.hi[r] + (float)o.lo[r];
+}
+
+// a_m[x] = sum_v d_v[x] Y_v[m][x],  Y_v[m][x] = sum_{u <= v} W[m][(u, v)] d_u[x].
+// A workgroup of 16 waves owns 512 grid points (32 per wave) and every shell m.  The
+// B operands (the fields d_u at the wave's points, 4 chunks of 16 shells) are built
+// once and stay in registers; d_v is read back from them.  The weight operands of
+// kAdjVG values of v at a time are staged in LDS (double buffered, reusing the LDS
+// that held the fields) and shared by all waves.
+constexpr int kAdjWaves = 16;
+constexpr int kAdjPts = 32 * kAdjWaves;
+constexpr int kAdjStride = kAdjPts + 1;
+constexpr int kAdjVG = 4;
+constexpr int kAdjWPerV = 4 * kAdjMaxMb * 2 * 64;   // uint4 words of W per v
+constexpr size_t kAdjLdsBytes = (size_t)(kAdjMaxMb * 32 + 1) * kAdjStride * 4;
+static_assert(2 * kAdjVG * kAdjWPerV * 16 <= kAdjLdsBytes, "weight stage must fit in the field buffer");
 
 template <int PREC>
 __global__ __launch_bounds__(64 * kAdjWaves, 1) void adjoint_gemm(const float* __restrict__ D,
-                                                                  const float* __restrict__ W,
-                                                                  const unsigned char* __restrict__ wmask,
-                                                                  const int* __restrict__ pair_uv,
-                                                                  int n_pairs_padded, int n_shells, int n_blk,
+                                                                  const uint4* __restrict__ W,
+                                                                  const int* __restrict__ vmask, int n_shells,
                                                                   long long G, float* __restrict__ A) {
-  __shared__ __attribute__((aligned(16))) float fld[(kMaxBlk * 16 + 1) * kAdjStride];
-  __shared__ __attribute__((aligned(16))) float wch[kMaxBlk * 16][32 + 4];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kAdjLdsBytes];
+  float* fld = reinterpret_cast<float*>(lds);
+  uint4* wst = reinterpret_cast<uint4*>(lds);   // [2][kAdjVG][kAdjWPerV] after the fields are consumed
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int g = lane >> 4, col = lane & 15;
+  const int hh = lane >> 5, col = lane & 31;
   const int b = blockIdx.y;
   const long long x0 = (long long)blockIdx.x * kAdjPts;
-  const int zrow = n_blk * 16;
   const float* Db = D + (size_t)b * n_shells * G;
-  for (int i = tid; i < (zrow + 1) * kAdjPts; i += 64 * kAdjWaves) {
+  for (int i = tid; i < 64 * kAdjPts; i += 64 * kAdjWaves) {
     const int s = i / kAdjPts, q = i % kAdjPts;
     fld[s * kAdjStride + q] = (s < n_shells) ? Db[(size_t)s * G + x0 + q] : 0.f;
   }
-  f32x4 acc[kMaxBlk];
+  __syncthreads();
+  const int pt = wave * 32 + col;
+  Operand<PREC> Bu[4];
 #pragma unroll
-  for (int mb = 0; mb < kMaxBlk; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const float* Wb = W + (size_t)b * n_shells * n_pairs_padded;
-  const int n_kc = n_pairs_padded / 32;
-  const int my_pt = wave * 16 + col;  // this lane's grid point (B column)
-  for (int kc = 0; kc < n_kc; ++kc) {
-    __syncthreads();
-    for (int i = tid; i < zrow * 32; i += 64 * kAdjWaves) {
-      const int m = i / 32, q = i % 32;
-      wch[m][q] = (m < n_shells) ? Wb[(size_t)m * n_pairs_padded + kc * 32 + q] : 0.f;
-    }
-    __syncthreads();
-    bool any = false;
-#pragma unroll
-    for (int mb = 0; mb < kMaxBlk; ++mb) any |= (mb < n_blk) && wmask[kc * kMaxBlk + mb];
-    if (!any) continue;
-    // B operand: pair products of pairs kc*32 + 8g + r at this lane's point
+  for (int uc = 0; uc < 4; ++uc) {
     float x[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int uv = pair_uv[kc * 32 + 8 * g + r];
-      const int u = uv & 0xffff, v = uv >> 16;
-      x[r] = fld[u * kAdjStride + my_pt] * fld[v * kAdjStride + my_pt];
-    }
-    const Operand<PREC> Bop = make_operand<PREC>(x, 1.f);
+    for (int r = 0; r < 8; ++r) x[r] = fld[(16 * uc + 8 * hh + r) * kAdjStride + pt];
+    Bu[uc] = make_operand<PREC>(x, 1.f);
+  }
+  __syncthreads();   // the field buffer becomes the weight stage
+
+  const uint4* Wb = W + (size_t)b * n_shells * kAdjWPerV;
+  const int n_stages = (n_shells + kAdjVG - 1) / kAdjVG;
+  constexpr int kPerThread = kAdjVG * kAdjWPerV / (64 * kAdjWaves);
+  uint4 wpre[kPerThread];
+  auto w_fetch = [&](int stage) {
 #pragma unroll
-    for (int mb = 0; mb < kMaxBlk; ++mb) {
-      if (mb >= n_blk || !wmask[kc * kMaxBlk + mb]) continue;
-      float w8[8];
-      load_row8(&wch[mb * 16 + col][0], g, w8);
-      const Operand<PREC> Aop = make_operand<PREC>(w8, 1.f);
-      mma<PREC>(acc[mb], Aop, Bop);
+    for (int k = 0; k < kPerThread; ++k) {
+      const int i = tid + k * 64 * kAdjWaves;
+      const int v = stage * kAdjVG + i / kAdjWPerV;
+      wpre[k] = v < n_shells ? Wb[(size_t)v * kAdjWPerV + i % kAdjWPerV] : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto w_store = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) wst[buf * kAdjVG * kAdjWPerV + tid + k * 64 * kAdjWaves] = wpre[k];
+  };
+  w_fetch(0);
+  w_store(0);
+  __syncthreads();
+
+  f32x16 acc[kAdjMaxMb];
+#pragma unroll
+  for (int mb = 0; mb < kAdjMaxMb; ++mb)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[mb][i] = 0.f;
+
+#pragma unroll
+  for (int vc = 0; vc < 4; ++vc) {            // fully unrolled: register indices stay static
+    if (16 * vc >= n_shells) break;
+    const Operand<PREC>& Bv = Bu[vc];
+#pragma unroll
+    for (int vv = 0; vv < 16; ++vv) {
+      const int v = 16 * vc + vv;
+      if (v >= n_shells) break;
+      const int st = v / kAdjVG, vi = v % kAdjVG;
+      if (vi == 0 && st + 1 < n_stages) w_fetch(st + 1);
+      const int mask = __builtin_amdgcn_readfirstlane(vmask[v]);   // bit 2 uc + mb
+      const uint4* wv = wst + ((st & 1) * kAdjVG + vi) * kAdjWPerV;
+      // d_v at this lane's point: element vv % 8 of chunk vc, held by the half vv / 8
+      const float own = operand_value<PREC>(Bv, vv % 8);
+      const float other = __shfl_xor(own, 32);
+      const float dv = (hh == vv / 8) ? own : other;
+#pragma unroll
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+        if (!(mask & (0x55 << mb))) continue;   // no weight in this shell block of m
+        f32x16 Y;
+#pragma unroll
+        for (int uc = 0; uc <= vc; ++uc) {
+          const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
+          const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
+          if (uc == 0) mma32_first<PREC>(Y, Wop, Bu[0]);
+          else mma32<PREC>(Y, Wop, Bu[uc]);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[mb][i] += dv * Y[i];
+      }
+      if (vi == kAdjVG - 1 || v + 1 == n_shells) {
+        if (st + 1 < n_stages) {
+          __syncthreads();          // every wave is done with the other buffer
+          w_store((st + 1) & 1);
+          __syncthreads();
+        }
+      }
     }
   }
-  // acc[mb]: lane l, reg r -> row m = 16 mb + 4 (l / 16) + r, column = point l % 16
-  float* Ab = A + (size_t)b * n_shells * G;
+  // acc[mb]: lane l, register i -> row m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4, point l % 32
+  float* Ab = A + (size_t)b * n_shells * G + x0 + pt;
 #pragma unroll
-  for (int mb = 0; mb < kMaxBlk; ++mb) {
-    if (mb >= n_blk) continue;
+  for (int mb = 0; mb < kAdjMaxMb; ++mb) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = mb * 16 + 4 * g + r;
-      if (m < n_shells) Ab[(size_t)m * G + x0 + wave * 16 + col] = acc[mb][r];
+    for (int i = 0; i < 16; ++i) {
+      const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+      if (m < n_shells) Ab[(size_t)m * G] = acc[mb][i];
     }
   }
 }
@@ -550,25 +698,20 @@ hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, co
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, const int* pair_uv,
-                                  int n_pairs, int n_pairs_padded, int n_shells, int n_closing, float* W, int batch,
-                                  hipStream_t st) {
-  dim3 grid((n_pairs_padded + 255) / 256, n_shells, batch);
-  hipLaunchKernelGGL(adjoint_weights, grid, dim3(256), 0, st, grad, fnorm, lookup, pair_uv, n_pairs, n_pairs_padded,
-                     n_shells, n_closing, W);
+hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
+                                  int n_closing, int prec, uint4* W, int batch, hipStream_t st) {
+  dim3 grid(64, n_shells, batch);
+  hipLaunchKernelGGL(adjoint_weights, grid, dim3(64), 0, st, grad, fnorm, lookup, n_shells, n_closing, prec, W);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_gemm(int prec, const float* D, const float* W, const unsigned char* wmask,
-                               const int* pair_uv, int n_pairs_padded, int n_shells, int n_blk, long long G,
+hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,
                                float* A, int batch, hipStream_t st) {
   dim3 grid((unsigned)(G / kAdjPts), batch);
   if (prec == kFP32)
-    hipLaunchKernelGGL(adjoint_gemm<kFP32>, grid, dim3(64 * kAdjWaves), 0, st, D, W, wmask, pair_uv, n_pairs_padded,
-                       n_shells, n_blk, G, A);
+    hipLaunchKernelGGL(adjoint_gemm<kFP32>, grid, dim3(64 * kAdjWaves), 0, st, D, W, vmask, n_shells, G, A);
   else
-    hipLaunchKernelGGL(adjoint_gemm<kBF16>, grid, dim3(64 * kAdjWaves), 0, st, D, W, wmask, pair_uv, n_pairs_padded,
-                       n_shells, n_blk, G, A);
+    hipLaunchKernelGGL(adjoint_gemm<kBF16>, grid, dim3(64 * kAdjWaves), 0, st, D, W, vmask, n_shells, G, A);
   return hipGetLastError();
 }
 

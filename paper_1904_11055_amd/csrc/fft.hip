@@ -20,16 +20,22 @@
 namespace ps {
 
 constexpr int kFftThreads = 256;
+constexpr int kAbsmaxSpread = 256;   // partial maxima per field (spreads the atomics)
 
+// Complex values held by one block: column passes (P1, P2, Q2, Q1) take more
+// pencils per block so that their strided global accesses come in longer runs;
+// row passes (P3, Q3) take fewer, for more resident blocks per CU.
 template <typename T>
 struct FftCfg;
 template <>
 struct FftCfg<float> {
-  static constexpr int kElems = 4096;  // complex values per block (32 KiB of LDS)
+  static constexpr int kElems = 4096;
+  static constexpr int kRowElems = 2048;
 };
 template <>
 struct FftCfg<double> {
-  static constexpr int kElems = 2048;  // 32 KiB of LDS
+  static constexpr int kElems = 2048;
+  static constexpr int kRowElems = 2048;
 };
 
 // ---------------------------------------------------------------------------
@@ -80,16 +86,63 @@ __device__ __forceinline__ void dftR(cplx<T>* v) {
   else dft8<T, S>(v);
 }
 
+// LDS position of element i of a pencil: one pad slot after every 8 elements, so the
+// stride-8 writes of the first radix-8 stage fall in distinct banks.
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+
+// Pencil stride in LDS: padded length plus one, so that neighbouring pencils start
+// in different banks.
+template <int N>
+constexpr int pencil_stride() { return N + N / 8 + 1; }
+
+// Twiddles of every stage but the first (whose twiddles are all 1), laid out
+// [stage][r - 1][k] so that lanes handling consecutive k read consecutive words.
+template <int N>
+constexpr int stage_tw_size() {
+  int l2 = 0;
+  while ((1 << l2) < N) ++l2;
+  int p = 1, tot = 0;
+  for (int s = 0; s < l2 / 3; ++s) {
+    if (p > 1) tot += 7 * p;
+    p *= 8;
+  }
+  if (l2 % 3) tot += (l2 % 3 == 2 ? 3 : 1) * p;
+  return tot;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void build_stage_twiddles(cplx<T>* stw, const cplx<T>* __restrict__ tw) {
+  constexpr int L2 = __builtin_ctz(N), N8 = L2 / 3, REM = L2 % 3;
+  int off = 0, p = 1;
+  for (int st = 0; st < N8; ++st) {
+    if (p > 1) {
+      for (int i = threadIdx.x; i < 7 * p; i += kFftThreads) {
+        const int r = i / p + 1, k = i % p;
+        stw[off + i] = tw[k * r * (N / (p * 8))];
+      }
+      off += 7 * p;
+    }
+    p *= 8;
+  }
+  if constexpr (REM != 0) {
+    constexpr int R = REM == 2 ? 4 : 2;
+    for (int i = threadIdx.x; i < (R - 1) * p; i += kFftThreads) {
+      const int r = i / p + 1, k = i % p;
+      stw[off + i] = tw[k * r * (N / (p * R))];
+    }
+  }
+}
+
 // One Stockham stage of radix R over P pencils of length N stored with stride NS.
 // After the stage every run of p*R consecutive outputs is a finished sub-DFT.
+// tws: this stage's twiddle table, entry (r - 1) * p + k = exp(2 pi i k r / (p R)).
 template <typename T, int N, int P, int NS, int R, int S>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, int p, const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int p, const cplx<T>* tws) {
   constexpr int NB = N / R;
   constexpr int BPT = (P * NB) / kFftThreads;
   static_assert(BPT >= 1 && (P * NB) % kFftThreads == 0, "block shape");
   cplx<T> v[BPT][R];
   const int tid = threadIdx.x;
-  const int stride_e = N / (p * R);
 #pragma unroll
   for (int u = 0; u < BPT; ++u) {
     const int b = tid + u * kFftThreads;
@@ -98,9 +151,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int p, const cplx<T>* __
     const cplx<T>* base = buf + pen * NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      cplx<T> x = base[i + r * NB];
+      cplx<T> x = base[pad8(i + r * NB)];
       if (r > 0 && p > 1) {
-        cplx<T> w = tw[k * r * stride_e];
+        cplx<T> w = tws[(r - 1) * p + k];
         if (S < 0) w.im = -w.im;
         x = cmul(x, w);
       }
@@ -117,25 +170,26 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int p, const cplx<T>* __
     const int j = (i - k) * R + k;
     cplx<T>* base = buf + pen * NS;
 #pragma unroll
-    for (int r = 0; r < R; ++r) base[j + r * p] = v[u][r];
+    for (int r = 0; r < R; ++r) base[pad8(j + r * p)] = v[u][r];
   }
   __syncthreads();
 }
 
 // Full length-N transform of the P pencils in buf (caller has synchronised).
 template <typename T, int N, int P, int NS, int S>
-__device__ __forceinline__ void fft_block(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
-  int p = 1;
+__device__ __forceinline__ void fft_block(cplx<T>* buf, const cplx<T>* stw) {
+  int p = 1, off = 0;
   constexpr int L2 = __builtin_ctz(N);
   constexpr int N8 = L2 / 3;
   constexpr int REM = L2 % 3;
 #pragma unroll
-  for (int s = 0; s < N8; ++s) {
-    fft_stage<T, N, P, NS, 8, S>(buf, p, tw);
+  for (int st = 0; st < N8; ++st) {
+    fft_stage<T, N, P, NS, 8, S>(buf, p, stw + off);
+    if (p > 1) off += 7 * p;
     p *= 8;
   }
-  if constexpr (REM == 2) fft_stage<T, N, P, NS, 4, S>(buf, p, tw);
-  if constexpr (REM == 1) fft_stage<T, N, P, NS, 2, S>(buf, p, tw);
+  if constexpr (REM == 2) fft_stage<T, N, P, NS, 4, S>(buf, p, stw + off);
+  if constexpr (REM == 1) fft_stage<T, N, P, NS, 2, S>(buf, p, stw + off);
 }
 
 __device__ __forceinline__ int freq_of(int n, int N) { return n < N / 2 ? n : n - N; }
@@ -154,8 +208,10 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restr
                                                       cplx<T>* __restrict__ H1,
                                                       const cplx<T>* __restrict__ tw, Geom g) {
   constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
   const int s = geom_shell(g, z);
   const int b = geom_batch(g, z);
@@ -172,7 +228,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restr
   const size_t box_sz = (size_t)g.B0 * g.B2 * g.B0;
   const cplx<float>* bx = box + (size_t)b * box_sz;
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u / N, n = u % N;
@@ -196,18 +252,18 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restr
         }
       }
     }
-    buf[pp * NS + n] = val;
+    buf[pp * NS + pad8(n)] = val;
   }
   __syncthreads();
-  fft_block<T, N, P, NS, +1>(buf, tw);
+  fft_block<T, N, P, NS, +1>(buf, stw);
   // store H1[z][x1][c][a0 + pp]
   cplx<T>* out = H1 + (size_t)z * N * g.B2 * g.B0;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x1 = u / P;
     const int a = a0 + pp;
-    if (a < g.B0) out[((size_t)x1 * g.B2 + c) * g.B0 + a] = buf[pp * NS + x1];
+    if (a < g.B0) out[((size_t)x1 * g.B2 + c) * g.B0 + a] = buf[pp * NS + pad8(x1)];
   }
 }
 
@@ -218,8 +274,10 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
                                                       cplx<T>* __restrict__ H2,
                                                       const cplx<T>* __restrict__ tw, Geom g) {
   constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
   const int s = geom_shell(g, z);
   const int c0 = blockIdx.x * P;
@@ -229,7 +287,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
   if (c0 * c0 > qm) return;  // every column of this chunk lies outside the shell
   const cplx<T>* in = H1 + (size_t)z * N * g.B2 * g.B0 + (size_t)x1 * g.B2 * g.B0;
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u / N, n = u % N;
@@ -238,26 +296,27 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
     cplx<T> val{(T)0, (T)0};
     if (c < g.B2 && q0 >= -Kc && q0 <= Kc && q0 * q0 + c * c <= qm)
       val = in[(size_t)c * g.B0 + (q0 + Kc)];
-    buf[pp * NS + n] = val;
+    buf[pp * NS + pad8(n)] = val;
   }
   __syncthreads();
-  fft_block<T, N, P, NS, +1>(buf, tw);
+  fft_block<T, N, P, NS, +1>(buf, stw);
   cplx<T>* out = H2 + (size_t)z * N * N * g.B2;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x0 = u / P;
     const int c = c0 + pp;
-    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * N + x1) * g.B2 + c] = buf[pp * NS + x0];
+    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * N + x1) * g.B2 + c] = buf[pp * NS + pad8(x0)];
   }
 }
 
-// Build the packed two-row spectrum Z = A + iB of rows A, B (half spectra with
-// c <= cm, zero above) into an FFT pencil of length N.
+
+// Z[n] of the packed two-row spectrum Z = A + iB from rows A, B staged in LDS
+// (half spectra with entries c = 0..cm; zero above).
 template <typename T>
-__device__ __forceinline__ cplx<T> two_row_spectrum(const cplx<T>* rowA, const cplx<T>* rowB, int n,
-                                                    int N, int cm) {
-  int c = n <= N / 2 ? n : N - n;
+__device__ __forceinline__ cplx<T> two_row_spectrum(const cplx<T>* rowA, const cplx<T>* rowB, int n, int N,
+                                                    int cm) {
+  const int c = n <= N / 2 ? n : N - n;
   if (c > cm) return cplx<T>{(T)0, (T)0};
   cplx<T> A = rowA[c], B = rowB[c];
   if (c == 0) {  // the DC term of a real row is real
@@ -271,8 +330,16 @@ __device__ __forceinline__ cplx<T> two_row_spectrum(const cplx<T>* rowA, const c
   return cplx<T>{A.re - B.im, A.im + B.re};
 }
 
+// Largest q2 index that can be non-zero for shell s.
+__device__ __forceinline__ int col_max(const Geom& g, int qm) {
+  int cm = g.Kc;
+  while (cm * cm > qm) --cm;
+  return cm;
+}
+
 // P3 (full grid): rows (x0, x1) in pairs, complex-to-real over x2.
 // out[z * G + row * N + x2]; optional |value| maximum per z (as float bits).
+// Dynamic LDS: the 2P input rows, 2P (Kc + 1) complex values.
 // grid (N*N/2/P, 1, nz)
 template <int N>
 __global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restrict__ H2,
@@ -281,48 +348,70 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restr
                                                       unsigned* __restrict__ absmax,
                                                       const cplx<float>* __restrict__ tw, Geom g) {
   using T = float;
-  constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int P = FftCfg<T>::kRowElems / N;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  extern __shared__ cplx<float> raw[];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
-  const int s = geom_shell(g, z);
-  int cm = g.Kc;
-  {
-    const int qm = qmax[s];
-    while (cm * cm > qm) --cm;
-  }
+  const int cm = col_max(g, qmax[geom_shell(g, z)]);
+  const int W = cm + 1;
   const size_t G = (size_t)N * N * N;
   const int row0 = blockIdx.x * 2 * P;  // first of the block's 2P rows
   const cplx<T>* in = H2 + (size_t)z * N * N * g.B2 + (size_t)row0 * g.B2;
+  for (int u = threadIdx.x; u < 2 * P * W; u += kFftThreads) {
+    const int r = u / W, c = u - r * W;
+    raw[u] = in[(size_t)r * g.B2 + c];
+  }
+  __syncthreads();
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u / N, n = u % N;
-    buf[pp * NS + n] = two_row_spectrum<T>(in + (size_t)(2 * pp) * g.B2, in + (size_t)(2 * pp + 1) * g.B2, n, N, cm);
+    buf[pp * NS + pad8(n)] = two_row_spectrum<T>(raw + (2 * pp) * W, raw + (2 * pp + 1) * W, n, N, cm);
   }
   __syncthreads();
-  fft_block<T, N, P, NS, +1>(buf, tw);
+  fft_block<T, N, P, NS, +1>(buf, stw);
   float* o = out + (size_t)z * G + (size_t)row0 * N;
   float amax = 0.f;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < 2 * E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;  // output index within the 2P rows
     const int r = u / N, x2 = u % N;
-    const cplx<T> v = buf[(r >> 1) * NS + x2];
+    const cplx<T> v = buf[(r >> 1) * NS + pad8(x2)];
     const float val = (r & 1) ? v.im : v.re;
     o[u] = val;
     amax = fmaxf(amax, fabsf(val));
   }
   if (absmax != nullptr) {
+    // block maximum, then one atomic into one of kAbsmaxSpread words of this field
+    __shared__ float wmax[kFftThreads / 64];
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(absmax + z, __float_as_uint(amax));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float m = wmax[0];
+      for (int w = 1; w < kFftThreads / 64; ++w) m = fmaxf(m, wmax[w]);
+      atomicMax(absmax + (size_t)z * kAbsmaxSpread + (blockIdx.x % kAbsmaxSpread), __float_as_uint(m));
+    }
   }
+}
+
+// absmax[z] = max over the kAbsmaxSpread partial maxima of field z (float bits).
+__global__ void reduce_absmax(const unsigned* __restrict__ part, unsigned* __restrict__ absmax, int nz) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nz) return;
+  unsigned m = 0;
+  for (int i = 0; i < kAbsmaxSpread; ++i) m = max(m, part[(size_t)z * kAbsmaxSpread + i]);
+  absmax[z] = m;
 }
 
 // P3 (symmetry wedge, float64): rows from a list, outputs x2 in [x1, N/2] only,
 // written compactly at out[z * nwedge + off(row) + x2 - x1].  rows[] holds
-// (x0, x1, off) triples; rows are processed two at a time.  grid (ceil(nrows/2/P), 1, nz)
+// (x0, x1, off) triples; rows are processed two at a time.  Dynamic LDS: the 2P
+// input rows.  grid (ceil(nrows/2/P), 1, nz)
 template <int N>
 __global__ __launch_bounds__(kFftThreads) void c2r_p3_wedge(const cplx<double>* __restrict__ H2,
                                                             const int* __restrict__ qmax,
@@ -331,38 +420,32 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3_wedge(const cplx<double>* 
                                                             const cplx<double>* __restrict__ tw,
                                                             Geom g) {
   using T = double;
-  constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int P = FftCfg<T>::kRowElems / N;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  extern __shared__ cplx<double> rawd[];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
-  const int s = geom_shell(g, z);
-  int cm = g.Kc;
-  {
-    const int qm = qmax[s];
-    while (cm * cm > qm) --cm;
-  }
+  const int cm = col_max(g, qmax[geom_shell(g, z)]);
+  const int W = cm + 1;
   const int r0 = blockIdx.x * 2 * P;
   const cplx<T>* in = H2 + (size_t)z * N * N * g.B2;
+  for (int u = threadIdx.x; u < 2 * P * W; u += kFftThreads) {
+    const int r = u / W, c = u - r * W;
+    const int rr = min(r0 + r, nrows - 1);  // rows past the end repeat the last one (unused)
+    rawd[u] = in[((size_t)rows[3 * rr] * N + rows[3 * rr + 1]) * g.B2 + c];
+  }
+  __syncthreads();
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 2
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u / N, n = u % N;
-    const int ra = r0 + 2 * pp, rb = ra + 1;
-    cplx<T> v{0, 0};
-    if (ra < nrows) {
-      const cplx<T>* rowA = in + ((size_t)rows[3 * ra] * N + rows[3 * ra + 1]) * g.B2;
-      const cplx<T>* rowB = rb < nrows ? in + ((size_t)rows[3 * rb] * N + rows[3 * rb + 1]) * g.B2 : nullptr;
-      if (rowB != nullptr) {
-        v = two_row_spectrum<T>(rowA, rowB, n, N, cm);
-      } else {
-        v = two_row_spectrum<T>(rowA, rowA, n, N, cm);  // imaginary output unused
-      }
-    }
-    buf[pp * NS + n] = v;
+    buf[pp * NS + pad8(n)] = two_row_spectrum<T>(rawd + (2 * pp) * W, rawd + (2 * pp + 1) * W, n, N, cm);
   }
   __syncthreads();
-  fft_block<T, N, P, NS, +1>(buf, tw);
+  fft_block<T, N, P, NS, +1>(buf, stw);
   double* o = out + (size_t)z * nwedge;
   for (int u = threadIdx.x; u < 2 * P * (N / 2 + 1); u += kFftThreads) {
     const int r = u / (N / 2 + 1), x2 = u % (N / 2 + 1);
@@ -370,7 +453,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3_wedge(const cplx<double>* 
     if (rr >= nrows) continue;
     const int x1 = rows[3 * rr + 1], off = rows[3 * rr + 2];
     if (x2 < x1) continue;
-    const cplx<T> v = buf[(r >> 1) * NS + x2];
+    const cplx<T> v = buf[(r >> 1) * NS + pad8(x2)];
     o[off + x2 - x1] = (r & 1) ? v.im : v.re;
   }
 }
@@ -386,28 +469,38 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ 
                                                       cplx<float>* __restrict__ H2,
                                                       const cplx<float>* __restrict__ tw, Geom g) {
   using T = float;
-  constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int P = FftCfg<T>::kRowElems / N;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
   const size_t G = (size_t)N * N * N;
   const int row0 = blockIdx.x * 2 * P;
   const float* src = in + (size_t)z * G + (size_t)row0 * N;
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 4
+  float ra[E], rb[E];
+#pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int u = threadIdx.x + m * kFftThreads;  // pencil pp = u / N, position x2
+    const int u = threadIdx.x + m * kFftThreads;
     const int pp = u / N, x2 = u % N;
-    buf[pp * NS + x2] = cplx<T>{src[(size_t)(2 * pp) * N + x2], src[(size_t)(2 * pp + 1) * N + x2]};
+    ra[m] = src[(size_t)(2 * pp) * N + x2];
+    rb[m] = src[(size_t)(2 * pp + 1) * N + x2];
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u / N, x2 = u % N;
+    buf[pp * NS + pad8(x2)] = cplx<T>{ra[m], rb[m]};
   }
   __syncthreads();
-  fft_block<T, N, P, NS, -1>(buf, tw);
+  fft_block<T, N, P, NS, -1>(buf, stw);
   cplx<T>* o = H2 + (size_t)z * N * N * g.B2 + (size_t)row0 * g.B2;
   for (int u = threadIdx.x; u < 2 * P * g.B2; u += kFftThreads) {
     const int r = u / g.B2, c = u % g.B2;
     const int pp = r >> 1;
-    const cplx<T> Zp = buf[pp * NS + c];
-    const cplx<T> Zm = buf[pp * NS + ((N - c) & (N - 1))];
+    const cplx<T> Zp = buf[pp * NS + pad8(c)];
+    const cplx<T> Zm = buf[pp * NS + pad8(((N - c) & (N - 1)))];
     cplx<T> v;
     if ((r & 1) == 0) {  // A = (Z[c] + conj(Z[-c])) / 2
       v = cplx<T>{(T)0.5 * (Zp.re + Zm.re), (T)0.5 * (Zp.im - Zm.im)};
@@ -425,29 +518,31 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q2(const cplx<float>* __restr
                                                       const cplx<float>* __restrict__ tw, Geom g) {
   using T = float;
   constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
   const int c0 = blockIdx.x * P;
   const int x1 = blockIdx.y;
   const cplx<T>* in = H2 + (size_t)z * N * N * g.B2;
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x0 = u / P;
     const int c = c0 + pp;
-    buf[pp * NS + x0] = (c < g.B2) ? in[((size_t)x0 * N + x1) * g.B2 + c] : cplx<T>{0, 0};
+    buf[pp * NS + pad8(x0)] = (c < g.B2) ? in[((size_t)x0 * N + x1) * g.B2 + c] : cplx<T>{0, 0};
   }
   __syncthreads();
-  fft_block<T, N, P, NS, -1>(buf, tw);
+  fft_block<T, N, P, NS, -1>(buf, stw);
   cplx<T>* o = H1 + (size_t)z * N * g.B2 * g.B0 + (size_t)x1 * g.B2 * g.B0;
   for (int u = threadIdx.x; u < P * g.B0; u += kFftThreads) {
     const int pp = u / g.B0, a = u % g.B0;
     const int c = c0 + pp;
     if (c >= g.B2) continue;
     const int q0 = a - g.Kc;
-    o[(size_t)c * g.B0 + a] = buf[pp * NS + (q0 & (N - 1))];
+    o[(size_t)c * g.B0 + a] = buf[pp * NS + pad8((q0 & (N - 1)))];
   }
 }
 
@@ -463,8 +558,10 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q1(const cplx<float>* __restr
                                                       const cplx<float>* __restrict__ tw, Geom g) {
   using T = float;
   constexpr int P = FftCfg<T>::kElems / N;
-  constexpr int NS = N + 1;
+  constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
+  __shared__ cplx<T> stw[stage_tw_size<N>()];
+  build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
   const int s = geom_shell(g, z);
   const int b = geom_batch(g, z);
@@ -480,15 +577,15 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q1(const cplx<float>* __restr
   }
   const cplx<T>* in = H1 + (size_t)z * N * g.B2 * g.B0;
   constexpr int E = P * N / kFftThreads;
-#pragma unroll 4
+#pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x1 = u / P;
     const int a = a0 + pp;
-    buf[pp * NS + x1] = (a < g.B0) ? in[((size_t)x1 * g.B2 + c) * g.B0 + a] : cplx<T>{0, 0};
+    buf[pp * NS + pad8(x1)] = (a < g.B0) ? in[((size_t)x1 * g.B2 + c) * g.B0 + a] : cplx<T>{0, 0};
   }
   __syncthreads();
-  fft_block<T, N, P, NS, -1>(buf, tw);
+  fft_block<T, N, P, NS, -1>(buf, stw);
   cplx<float>* o = box + (size_t)b * g.B0 * g.B2 * g.B0;
   for (int u = threadIdx.x; u < P * g.B0; u += kFftThreads) {
     const int pp = u / g.B0, e = u % g.B0;
@@ -497,7 +594,7 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q1(const cplx<float>* __restr
     const int q0 = a - Kc, q1 = e - Kc;
     const int Q = q0 * q0 + q1 * q1 + c * c;
     const size_t idx = ((size_t)a * g.B2 + c) * g.B0 + e;
-    const cplx<T> v = buf[pp * NS + (q1 & (N - 1))];
+    const cplx<T> v = buf[pp * NS + pad8((q1 & (N - 1)))];
     if (MASK) {
       if (Q <= qm && shell_of_q[Q] == s) o[idx] = v;
     } else {
@@ -561,11 +658,12 @@ hipError_t launch_c2r_p2(const cplx<T>* H1, const int* qmax, cplx<T>* H2, const 
 
 hipError_t launch_c2r_p3(const cplx<float>* H2, const int* qmax, float* out, unsigned* absmax,
                          const cplx<float>* tw, Geom g, int nz, hipStream_t st) {
-  const int P = FftCfg<float>::kElems / g.N;
+  const int P = FftCfg<float>::kRowElems / g.N;
   dim3 grid(g.N * g.N / 2 / P, 1, nz);
+  const size_t shm = (size_t)2 * P * g.B2 * sizeof(cplx<float>);
   switch (g.N) {
 #define CASE(n) \
-  case n: hipLaunchKernelGGL((c2r_p3<n>), grid, dim3(kFftThreads), 0, st, H2, qmax, out, absmax, tw, g); break;
+  case n: hipLaunchKernelGGL((c2r_p3<n>), grid, dim3(kFftThreads), shm, st, H2, qmax, out, absmax, tw, g); break;
     PS_FOR_EACH_N(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -576,13 +674,14 @@ hipError_t launch_c2r_p3(const cplx<float>* H2, const int* qmax, float* out, uns
 hipError_t launch_c2r_p3_wedge(const cplx<double>* H2, const int* qmax, const int* rows, int nrows,
                                double* out, long long nwedge, const cplx<double>* tw, Geom g, int nz,
                                hipStream_t st) {
-  const int P = FftCfg<double>::kElems / g.N;
+  const int P = FftCfg<double>::kRowElems / g.N;
   dim3 grid((nrows + 2 * P - 1) / (2 * P), 1, nz);
+  const size_t shm = (size_t)2 * P * g.B2 * sizeof(cplx<double>);
   switch (g.N) {
-#define CASE(n)                                                                                       \
-  case n:                                                                                             \
-    hipLaunchKernelGGL((c2r_p3_wedge<n>), grid, dim3(kFftThreads), 0, st, H2, qmax, rows, nrows, out, \
-                       nwedge, tw, g);                                                                \
+#define CASE(n)                                                                                         \
+  case n:                                                                                               \
+    hipLaunchKernelGGL((c2r_p3_wedge<n>), grid, dim3(kFftThreads), shm, st, H2, qmax, rows, nrows, out, \
+                       nwedge, tw, g);                                                                  \
     break;
     PS_FOR_EACH_N(CASE)
 #undef CASE
@@ -593,7 +692,7 @@ hipError_t launch_c2r_p3_wedge(const cplx<double>* H2, const int* qmax, const in
 
 hipError_t launch_r2c_q3(const float* in, cplx<float>* H2, const cplx<float>* tw, Geom g, int nz,
                          hipStream_t st) {
-  const int P = FftCfg<float>::kElems / g.N;
+  const int P = FftCfg<float>::kRowElems / g.N;
   dim3 grid(g.N * g.N / 2 / P, 1, nz);
   switch (g.N) {
 #define CASE(n) case n: hipLaunchKernelGGL((r2c_q3<n>), grid, dim3(kFftThreads), 0, st, in, H2, tw, g); break;
@@ -629,6 +728,11 @@ hipError_t launch_r2c_q1(const cplx<float>* H1, const int16_t* sq, const int* qm
 #undef CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_absmax(const unsigned* part, unsigned* absmax, int nz, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_absmax, dim3((nz + 255) / 256), dim3(256), 0, st, part, absmax, nz);
   return hipGetLastError();
 }
 

@@ -27,6 +27,8 @@ hipError_t launch_r2c_q2(const cplx<float>* H2, cplx<float>* H1, const cplx<floa
 template <bool MASK>
 hipError_t launch_r2c_q1(const cplx<float>* H1, const int16_t* shell_of_q, const int* qmax, cplx<float>* box,
                          const cplx<float>* tw, Geom g, int nz, hipStream_t st);
+constexpr int kAbsmaxSpreadHost = 256;
+hipError_t launch_reduce_absmax(const unsigned* part, unsigned* absmax, int nz, hipStream_t st);
 hipError_t launch_box_from_half_spectrum(const cplx<float>* hs, cplx<float>* box, Geom g, int batch,
                                          hipStream_t st);
 
@@ -34,7 +36,8 @@ hipError_t launch_box_from_half_spectrum(const cplx<float>* hs, cplx<float>* box
 struct CtrParams {
   const float* D;
   const int* pair_uv;
-  const int* slots;
+  const int* slot_uni;     // [n_groups][waves][kSlots / 4]: one byte per slot
+  const int* slot_lane;    // [n_groups][waves][16 rows][kSlots]: pair shells per lane
   const int* slot_tile;
   const unsigned* absmax;
   float* partials;
@@ -46,10 +49,14 @@ struct CtrParams {
   int ksteps;
   int n_chunks;
 };
-constexpr int kCtrWavesHost = 8;
-constexpr int kSlotsHost = 32;
+constexpr int kCtrWavesHost = 16;
+constexpr int kSlotsHost = 14;
+constexpr int kSlots4Host = 12;
+constexpr int kSlots2Host = 4;
+constexpr int kSlotsMaxHost = 16;   // per-wave stride of the slot tables
+constexpr int kStagePtsHost = 64;
 constexpr int kMaxBlkHost = 4;
-constexpr int kAdjPtsHost = 128;
+constexpr int kAdjPtsHost = 512;   // grid points per adjoint workgroup
 constexpr int kCntTuplesPerGroup = 1024;
 constexpr int kCntStageHost = 32;
 
@@ -64,14 +71,13 @@ hipError_t launch_gather(const double* tmp, int n_groups, long long n_ent, const
 hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, const unsigned char* wmult,
                                const int* cand, int n_cand, int n_shells, int stages_per_chunk, int n_chunks,
                                double* part, hipStream_t st);
-hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, const int* pair_uv,
-                                  int n_pairs, int n_pairs_padded, int n_shells, int n_closing, float* W, int batch,
-                                  hipStream_t st);
-hipError_t launch_adjoint_gemm(int prec, const float* D, const float* W, const unsigned char* wmask,
-                               const int* pair_uv, int n_pairs_padded, int n_shells, int n_blk, long long G,
+hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
+                                  int n_closing, int prec, uint4* W, int batch, hipStream_t st);
+hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,
                                float* A, int batch, hipStream_t st);
 
 // util.hip
 hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_t st);
+hipError_t launch_fields_absmax(const float* x, long long G, int nz, unsigned* part, int spread, hipStream_t st);
 
 }  // namespace ps

@@ -90,10 +90,11 @@ struct polyspec_plan_s {
   // contraction tiling
   int n_pairs = 0, n_pairs_padded = 0, n_tiles = 0, n_groups = 0, ksteps = 0, n_chunks = 0;
   int red_groups = 0, red_cpg = 0;
+  int n_adj_active = 0;
   std::vector<int> pair_uv;
 
   // device tables
-  DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_tile_d, ent_d, bins_d, fnorm_d, lookup_d, wmask_d, flag_d;
+  DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_lane_d, slot_tile_d, ent_d, bins_d, fnorm_d, lookup_d, wmask_d, flag_d;
   // workspace carving
   DevBuf own_ws;
   char* ws = nullptr;
@@ -106,7 +107,9 @@ struct polyspec_plan_s {
   float* A = nullptr;
   float* partials = nullptr;
   double* red = nullptr;
-  unsigned* absmax = nullptr;
+  unsigned* absmax = nullptr;       // per-field max |d| (float bits), FP16 scaling
+  unsigned* absmax_part = nullptr;  // partial maxima written by the shell transform
+  bool absmax_valid = false;
   float* W = nullptr;
   bool have_fields = false;
 
@@ -250,8 +253,8 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   L.A = (p->order == 3) ? L.D : 0;
   L.partials = align256((size_t)p->batch * p->n_chunks * (size_t)p->n_tiles * 256 * sizeof(float));
   L.red = align256((size_t)p->batch * p->red_groups * (size_t)p->n_tiles * 256 * sizeof(double));
-  L.absmax = align256(zf * sizeof(unsigned));
-  L.W = (p->order == 3) ? align256((size_t)p->batch * p->nb * p->n_pairs_padded * sizeof(float)) : 0;
+  L.absmax = align256(zf * sizeof(unsigned)) + align256(zf * ps::kAbsmaxSpreadHost * sizeof(unsigned));
+  L.W = (p->order == 3) ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16) : 0;
   L.total = L.box + L.gbox + L.H1 + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
   return L;
 }
@@ -267,7 +270,9 @@ void carve(polyspec_plan_s* p, char* base) {
   p->A = L.A ? (float*)c : nullptr; c += L.A;
   p->partials = (float*)c; c += L.partials;
   p->red = (double*)c; c += L.red;
-  p->absmax = (unsigned*)c; c += L.absmax;
+  p->absmax = (unsigned*)c;
+  p->absmax_part = (unsigned*)(c + align256((size_t)p->batch * p->nb * sizeof(unsigned)));
+  c += L.absmax;
   p->W = L.W ? (float*)c : nullptr; c += L.W;
 }
 
@@ -377,6 +382,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
     t = u;
   }
   // greedy: largest units first, onto the least loaded wave with room
+  const int cap = n == 2 ? ps::kSlots2Host : n == 3 ? ps::kSlotsHost : ps::kSlots4Host;
   std::vector<int> order(units.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(),
@@ -388,40 +394,60 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
   std::vector<std::vector<Wave>> groups;
   auto new_group = [&]() { groups.emplace_back(ps::kCtrWavesHost); };
   new_group();
-  const double form_cost = 1.0, tile_cost = 1.0;
   for (int ui : order) {
     const int cnt = units[ui].second;
-    if (cnt > ps::kSlotsHost) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "tile unit larger than a wave");
+    if (cnt > cap) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "tile unit larger than a wave");
     Wave* best = nullptr;
     for (auto& grp : groups)
       for (auto& w : grp)
-        if ((int)w.tiles.size() + cnt <= ps::kSlotsHost && (!best || w.load < best->load)) best = &w;
+        if ((int)w.tiles.size() + cnt <= cap && (!best || w.load < best->load)) best = &w;
     if (!best) {
       new_group();
       best = &groups.back()[0];
     }
     for (int k = 0; k < cnt; ++k) best->tiles.push_back(units[ui].first + k);
-    best->load += form_cost + tile_cost * cnt * (n == 4 ? 2.0 : 1.0);
+    best->load += 1.0 + cnt * (n == 4 ? 2.0 : 1.0);   // one A formation + the tiles
   }
   p->n_groups = (int)groups.size();
-  std::vector<int> slots(p->n_groups * ps::kCtrWavesHost * ps::kSlotsHost, -1);
-  std::vector<int> slot_tile(slots.size(), -1);
+  // slot tables (see contract_tiles): a uniform byte per slot and per-lane pair shells,
+  // laid out with the fixed per-wave stride kSlotsMaxHost
+  const int S = ps::kSlotsMaxHost;
+  std::vector<int> uni((size_t)p->n_groups * ps::kCtrWavesHost * (S / 4), 0);
+  std::vector<int> lanew((size_t)p->n_groups * ps::kCtrWavesHost * 16 * S, 0);
+  std::vector<int> slot_tile((size_t)p->n_groups * ps::kCtrWavesHost * S, -1);
+  auto uv8 = [&](int pair) {
+    const int w = p->pair_uv[pair];
+    return (w & 0xff) | (((w >> 16) & 0xff) << 8);
+  };
   for (int gi = 0; gi < p->n_groups; ++gi)
     for (int w = 0; w < ps::kCtrWavesHost; ++w) {
       auto& tl = groups[gi][w].tiles;
       std::sort(tl.begin(), tl.end());
+      const size_t gw = (size_t)gi * ps::kCtrWavesHost + w;
       int prev_a = -1;
-      for (size_t s = 0; s < tl.size(); ++s) {
-        const TileKey k = tlist[tl[s]];
-        int word = (k.a & 0xfff) | ((k.b & 0xfff) << 12);
-        if (k.a != prev_a) word |= 1 << 24;
-        prev_a = k.a;
-        const size_t at = ((size_t)gi * ps::kCtrWavesHost + w) * ps::kSlotsHost + s;
-        slots[at] = word;
-        slot_tile[at] = tl[s];
+      for (int s = 0; s < S; ++s) {
+        int info = 0x80;
+        if (s >= cap) {  // beyond this order's slot count: never read
+          uni[gw * (S / 4) + s / 4] |= info << (8 * (s % 4));
+          continue;
+        }
+        if (s < (int)tl.size()) {
+          const TileKey k = tlist[tl[s]];
+          const int form = k.a != prev_a ? 1 : 0;
+          prev_a = k.a;
+          info = (n == 4 ? 0 : (k.b & 3)) | (n == 2 ? (k.a & 3) << 2 : 0) | (form << 4);
+          slot_tile[gw * S + s] = tl[s];
+          for (int r = 0; r < 16; ++r) {
+            int& word = lanew[(gw * 16 + r) * S + (n == 4 ? s : s / 2)];
+            if (n == 3) word |= uv8(16 * k.a + r) << (16 * (s % 2));
+            if (n == 4) word = uv8(16 * k.a + r) | (uv8(16 * k.b + r) << 16);
+          }
+        }
+        uni[gw * (S / 4) + s / 4] |= info << (8 * (s % 4));
       }
     }
-  PS_TRY(upload(p, &p->slots_d, slots));
+  PS_TRY(upload(p, &p->slots_d, uni));
+  PS_TRY(upload(p, &p->slot_lane_d, lanew));
   PS_TRY(upload(p, &p->slot_tile_d, slot_tile));
   PS_TRY(upload(p, &p->pairs_d, p->pair_uv));
   return POLYSPEC_OK;
@@ -607,7 +633,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   PS_TRY(build_tiles(p, &ent_of_cand));
 
   // chunking of the grid for the contraction
-  const long long steps = p->G / 32;
+  const long long steps = p->G / ps::kStagePtsHost;
   long long ks = steps / 512;
   ks = std::max(1LL, std::min(256LL, ks));
   while (steps % ks) --ks;
@@ -651,17 +677,17 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   PS_TRY(dev_alloc(p, &p->flag_d, 256));
   if (p->order == 3) {
     PS_TRY(upload(p, &p->lookup_d, lookup));
-    // which (32-pair chunk, 16-shell block) of W can be non-zero
-    const int n_kc = p->n_pairs_padded / 32;
-    std::vector<unsigned char> wmask((size_t)n_kc * ps::kMaxBlkHost, 0);
-    for (int pi = 0; pi < p->n_pairs; ++pi) {
-      const int u = p->pair_uv[pi] & 0xffff, v = p->pair_uv[pi] >> 16;
-      for (int m = 0; m < p->nb; ++m) {
-        int t[3] = {m, u, v};
-        std::sort(t, t + 3);
-        if (lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] >= 0) wmask[(pi / 32) * ps::kMaxBlkHost + m / 16] = 1;
-      }
-    }
+    // for each v: which (16-shell chunk of u, 32-shell block of m) of W[m][(u, v)] can
+    // be non-zero, as bits 2 uc + mb (the adjoint GEMM skips the others)
+    std::vector<int> wmask(p->nb, 0);
+    for (int v = 0; v < p->nb; ++v)
+      for (int u = 0; u <= v; ++u)
+        for (int m = 0; m < p->nb; ++m) {
+          int t[3] = {m, u, v};
+          std::sort(t, t + 3);
+          if (lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] >= 0) wmask[v] |= 1 << (2 * (u / 16) + m / 32);
+        }
+    p->n_adj_active = p->nb;
     PS_TRY(upload(p, &p->wmask_d, wmask));
   }
   return POLYSPEC_OK;
@@ -675,7 +701,7 @@ void release(polyspec_plan_s* p) {
   p->ev_pending.clear();
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   p->ev_pool.clear();
-  DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_tile_d, &p->ent_d,
+  DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_lane_d, &p->slot_tile_d, &p->ent_d,
                     &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->own_ws};
   for (DevBuf* b : bufs) dev_free(b);
 }
@@ -777,13 +803,17 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
                                        (const cplx<float>*)p->tw32.p, gin, p->batch, st));
   }
   Geom gs = make_geom(p, p->nb, 1);
-  PS_HIP(p, ps::launch_fill_u32(p->absmax, 0u, (size_t)nz, st));
+  const bool want_max = p->prec == POLYSPEC_SPLIT_FP16;
+  if (want_max) PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
   PS_TIMED(p, POLYSPEC_PH_SHELL_P1, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
                                             (const cplx<float>*)p->tw32.p, gs, nz, st));
   PS_TIMED(p, POLYSPEC_PH_SHELL_P2, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, (const cplx<float>*)p->tw32.p, gs, nz,
                                      st));
-  PS_TIMED(p, POLYSPEC_PH_SHELL_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D, p->absmax, (const cplx<float>*)p->tw32.p, gs,
-                              nz, st));
+  PS_TIMED(p, POLYSPEC_PH_SHELL_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D,
+                                                      want_max ? p->absmax_part : nullptr,
+                                                      (const cplx<float>*)p->tw32.p, gs, nz, st));
+  if (want_max) PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
+  p->absmax_valid = want_max;
   p->have_fields = true;
   return POLYSPEC_OK;
 }
@@ -793,10 +823,18 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_contract before polyspec_shells");
   hipStream_t st = p->stream;
+  if (p->prec == POLYSPEC_SPLIT_FP16 && !p->absmax_valid) {  // precision switched after polyspec_shells
+    const int nz = p->batch * p->nb;
+    PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
+    PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));
+    PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
+    p->absmax_valid = true;
+  }
   ps::CtrParams cp;
   cp.D = p->D;
   cp.pair_uv = (const int*)p->pairs_d.p;
-  cp.slots = (const int*)p->slots_d.p;
+  cp.slot_uni = (const int*)p->slots_d.p;
+  cp.slot_lane = (const int*)p->slot_lane_d.p;
   cp.slot_tile = (const int*)p->slot_tile_d.p;
   cp.absmax = p->absmax;
   cp.partials = p->partials;
@@ -837,11 +875,12 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
   const int nz = p->batch * p->nb;
   const int ncl = (int)p->closing.size();
   const int aprec = (p->prec == POLYSPEC_FP32) ? 0 : 1;  // FP16 mode uses the bf16 split here
-  PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS, ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p,
-                                       (const int*)p->pairs_d.p, p->n_pairs, p->n_pairs_padded, p->nb, ncl, p->W,
-                                       p->batch, st));
-  PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM, ps::launch_adjoint_gemm(aprec, p->D, p->W, (const unsigned char*)p->wmask_d.p, (const int*)p->pairs_d.p,
-                                    p->n_pairs_padded, p->nb, p->n_blk, p->G, p->A, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
+           ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb, ncl,
+                                      aprec, (uint4*)p->W, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
+           ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G, p->A,
+                                   p->batch, st));
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
   Geom gs = make_geom(p, p->nb, 1);

@@ -19,4 +19,21 @@ hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_
   return hipGetLastError();
 }
 
+// Partial maxima of |x| over each field z of length G (float bits), spread over
+// spread words per field; reduce_absmax then takes the maximum of each field's words.
+__global__ void fields_absmax(const float* __restrict__ x, long long G, unsigned* __restrict__ part, int spread) {
+  const int z = blockIdx.y;
+  const float* f = x + (size_t)z * G;
+  float m = 0.f;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < G; i += (long long)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(f[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(part + (size_t)z * spread + (blockIdx.x % spread), __float_as_uint(m));
+}
+
+hipError_t launch_fields_absmax(const float* x, long long G, int nz, unsigned* part, int spread, hipStream_t st) {
+  hipLaunchKernelGGL(fields_absmax, dim3(1024, nz), dim3(256), 0, st, x, G, part, spread);
+  return hipGetLastError();
+}
+
 }  // namespace ps

@@ -212,3 +212,17 @@ def test_state_and_guard_errors(gpu):
         p4.backward(torch.zeros(1, p4.n_closing, dtype=torch.float64, device="cuda:0"))
     assert e.value.status == 7
     p4.close()
+
+
+def test_precision_switch_after_shells(gpu):
+    import torch
+    ps = _ps()
+    delta = fieldgen.lognormal_field(64, 17).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 16, 1.0)
+    plan = ps.Plan(64, 3, 16, 1.0, precision=ps.SPLIT_BF16, device="cuda:0")
+    plan.shells(torch.from_numpy(delta)[None].to("cuda:0"))
+    for prec, tol in ((ps.SPLIT_FP16, 1e-4), (ps.FP32, 1e-5), (ps.SPLIT_BF16, 1e-4)):
+        plan.precision = prec
+        B = plan.contract().cpu().numpy()[0]
+        assert _rel(B, ref["B"]) < tol, prec
+    plan.close()
