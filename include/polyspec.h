@@ -46,7 +46,7 @@ typedef enum {
   POLYSPEC_ERR_ALIASING = 2,           /* order * (n_shells + 1/2) * width > N without ALLOW_ALIASING */
   POLYSPEC_ERR_OUT_OF_MEMORY = 3,      /* device or host allocation failed */
   POLYSPEC_ERR_DEVICE = 4,             /* a HIP runtime call or kernel launch failed */
-  POLYSPEC_ERR_COUNT_NOT_INTEGRAL = 5, /* a polygon count quotient was not within 1e-3 of an integer */
+  POLYSPEC_ERR_COUNT_NOT_INTEGRAL = 5, /* a count quotient q missed an integer by max(1e-3, |q| 2^-46) */
   POLYSPEC_ERR_STATE = 6,              /* call out of order (contract before shells, ...) */
   POLYSPEC_ERR_UNSUPPORTED = 7         /* valid request outside what this build implements */
 } polyspec_status;
@@ -85,8 +85,10 @@ typedef struct {
  * Validates the descriptor, builds the shell, tuple and tile tables, and computes
  * the polygon counts n_t of every candidate tuple on the device in float64 (the
  * estimator applied to unit shells, Sec. 4 and Appendix A).  Synchronises the
- * stream once to read the counts back.  Returns POLYSPEC_ERR_COUNT_NOT_INTEGRAL if
- * any count quotient misses an integer by 1e-3 or more.  *out receives the plan. */
+ * stream once to read the counts back.  The count sums are accumulated with
+ * compensated (double-double) additions; returns POLYSPEC_ERR_COUNT_NOT_INTEGRAL if
+ * any count quotient q misses an integer by max(1e-3, |q| 2^-46) or more, or if a
+ * count reaches 2^44.  *out receives the plan. */
 polyspec_status polyspec_plan(const polyspec_desc* desc, void* stream, polyspec_plan_t* out);
 
 /* Shell fields (Sec. 2, I_k(x); Appendix A, FFTW(I~)).  d_delta is a device

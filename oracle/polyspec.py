@@ -69,7 +69,8 @@ __all__ = [
     "shell_thresholds", "shell_of_squared_norm", "squared_norm_grid", "shell_id_grid",
     "outer_radius", "is_alias_free", "sorted_tuples", "candidate_tuples", "pair_list",
     "shell_mode_counts", "shell_fields", "shell_fields_from_hat", "count_fields",
-    "shell_fields_on_planes", "product_sums", "counts_from_sums", "polygon_counts",
+    "shell_fields_on_planes", "product_sums", "tuple_product_sums", "counts_from_sums", "polygon_counts",
+    "pair_counts", "polygon_counts_exact",
     "polyspectrum", "adjoint_weights", "gradient", "physical_factor",
 ]
 
@@ -224,11 +225,14 @@ def shell_fields_on_planes(delta_hat: np.ndarray, N: int, n_shells: int, width: 
 # Product sums (Sec. 2: "the matrix inner product" of the shell fields;
 # Appendix A: sum over [x] of prod_j FFTW(I~_{k_j})).
 # ----------------------------------------------------------------------------
-def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192) -> np.ndarray:
+def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192, compensated: bool = False):
     """S_t = sum_x prod_j fields[t_j - 1][x] in FP64, for orders 2, 3 and 4.
 
     The grid is summed in chunks; pair products d_i d_j are formed once per chunk
-    and multiplied against the remaining factor(s) with a matrix product.
+    and multiplied against the remaining factor(s) with a matrix product.  With
+    compensated=True the chunk results are added with error-free transformations
+    and the pair (hi, lo) with S = hi + lo is returned (used for polygon counts,
+    which reach 10^12 and must round to the right integer).
     """
     tuples = np.asarray(tuples, dtype=np.int64)
     order = tuples.shape[1]
@@ -238,49 +242,137 @@ def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192) -> n
     pairs = pair_list(nb)
     pidx = {(int(i), int(j)): n for n, (i, j) in enumerate(pairs)}
     if order == 2:
-        acc = np.zeros((nb, nb))
+        shape = (nb, nb)
     elif order == 3:
-        acc = np.zeros((len(pairs), nb))
+        shape = (len(pairs), nb)
     elif order == 4:
-        acc = np.zeros((len(pairs), len(pairs)))
+        shape = (len(pairs), len(pairs))
     else:
         raise ValueError("product_sums supports orders 2, 3 and 4")
+    acc = np.zeros(shape)
+    lo = np.zeros(shape) if compensated else None
     pi = pairs[:, 0] - 1
     pj = pairs[:, 1] - 1
     for x0 in range(0, G, chunk):
         blk = flat[:, x0:x0 + chunk]
         if order == 2:
-            acc += blk @ blk.T
-            continue
-        P = blk[pi] * blk[pj]
-        if order == 3:
-            acc += P @ blk.T
+            part = blk @ blk.T
         else:
-            acc += P @ P.T
-    if order == 2:
-        return acc[tuples[:, 0] - 1, tuples[:, 1] - 1]
-    if order == 3:
-        rows = np.array([pidx[(int(a), int(b))] for a, b in tuples[:, :2]], dtype=np.int64)
-        return acc[rows, tuples[:, 2] - 1]
-    rows = np.array([pidx[(int(a), int(b))] for a, b in tuples[:, :2]], dtype=np.int64)
-    cols = np.array([pidx[(int(a), int(b))] for a, b in tuples[:, 2:]], dtype=np.int64)
-    return acc[rows, cols]
+            P = blk[pi] * blk[pj]
+            part = P @ blk.T if order == 3 else P @ P.T
+        if compensated:      # two-sum: acc + part = s + err exactly
+            s_ = acc + part
+            bb = s_ - acc
+            lo += (acc - (s_ - bb)) + (part - bb)
+            acc = s_
+        else:
+            acc += part
+
+    def pick(a):
+        if order == 2:
+            return a[tuples[:, 0] - 1, tuples[:, 1] - 1]
+        rows = np.array([pidx[(int(u), int(v))] for u, v in tuples[:, :2]], dtype=np.int64)
+        if order == 3:
+            return a[rows, tuples[:, 2] - 1]
+        cols = np.array([pidx[(int(u), int(v))] for u, v in tuples[:, 2:]], dtype=np.int64)
+        return a[rows, cols]
+
+    return (pick(acc), pick(lo)) if compensated else pick(acc)
 
 
-def counts_from_sums(C: np.ndarray, N: int, tol: float = 1e-3) -> np.ndarray:
-    """n_t = rint(C_t / N^3); the quotient must be an integer to within tol."""
-    q = np.asarray(C, dtype=np.float64) / float(N) ** 3
-    n = np.rint(q)
-    bad = np.abs(q - n) >= tol
-    if bad.any():
-        raise ArithmeticError(f"polygon count not integral: worst {np.abs(q - n).max():.3e}")
+def tuple_product_sums(fields_by_shell: dict, tuples) -> np.ndarray:
+    """sum_x prod_j f_{t_j}[x] for each tuple, accumulated in extended precision."""
+    out = np.empty(len(tuples), dtype=np.float64)
+    for n, t in enumerate(tuples):
+        prod = np.array(fields_by_shell[int(t[0])], dtype=np.float64, copy=True)
+        for s in t[1:]:
+            prod *= fields_by_shell[int(s)]
+        out[n] = float(np.sum(prod, dtype=np.longdouble))
+    return out
+
+
+def counts_from_sums(C, N: int, tol: float = 1e-3) -> np.ndarray:
+    """n_t = rint(C_t / N^3); the quotient q must be an integer to within max(tol, |q| 2^-46).
+
+    C is an array of sums, or a (hi, lo) pair of arrays with C = hi + lo.  N^3 is a
+    power of two for the grids used here, so the division is exact.  The relative
+    part of the tolerance covers the FP64 rounding of the count fields, which for
+    counts near 10^12 reaches 1e-3 of a unit; counts of 2^44 or more are refused.
+    """
+    if isinstance(C, tuple):
+        hi, lo = (np.asarray(a, dtype=np.float64) for a in C)
+    else:
+        hi, lo = np.asarray(C, dtype=np.float64), np.zeros(np.shape(C))
+    qh, ql = hi / float(N) ** 3, lo / float(N) ** 3
+    n = np.rint(qh + ql)
+    frac = (qh - n) + ql
+    if np.any(np.abs(qh) >= 2.0 ** 44):
+        raise ArithmeticError("polygon count of 2^44 or more: beyond exact FP64 recovery")
+    lim = np.maximum(tol, np.ldexp(np.abs(qh), -46))
+    if np.any(np.abs(frac) >= lim):
+        raise ArithmeticError(f"polygon count not integral: worst {np.abs(frac).max():.3e}")
     return n.astype(np.int64)
 
 
 def polygon_counts(N: int, order: int, n_shells: int, width: float, tuples) -> np.ndarray:
     """Number of closed ordered vector n-tuples per tuple (Appendix A, count on a unit grid)."""
     c = count_fields(N, n_shells, width)
-    return counts_from_sums(product_sums(c, tuples), N)
+    return counts_from_sums(product_sums(c, tuples, chunk=2048, compensated=True), N)
+
+
+def pair_counts(c_i: np.ndarray, c_j: np.ndarray) -> np.ndarray:
+    """P_ij(q) = #{(q_1, q_2) : q_1 in S_i, q_2 in S_j, q_1 + q_2 = q mod N} on the rfftn layout.
+
+    c_i, c_j are the count fields of the two shells.  The DFT of c_i c_j is N^3 P_ij;
+    every value is a small integer (at most min(|S_i|, |S_j|)), so rounding the
+    FP64 transform recovers it exactly.
+    """
+    N = c_i.shape[0]
+    P = rfftn(c_i * c_j)
+    P /= float(N) ** 3
+    R = np.rint(P.real)
+    if np.abs(P.real - R).max() >= 1e-3 or np.abs(P.imag).max() >= 1e-3:
+        raise ArithmeticError("pair count not integral")
+    return R.astype(np.int64)
+
+
+def polygon_counts_exact(N: int, order: int, n_shells: int, width: float, tuples) -> np.ndarray:
+    """The counts of polygon_counts, summed in integers from pair counts.
+
+    A closed ordered tuple q_1 + ... + q_n = 0 (mod N) splits as q_1 + q_2 = q and
+    q_3 (+ q_4) = -q, so n_ijk = sum_{q in S_k} P_ij(q) and n_ijkl = sum_q P_ij(q) P_kl(q)
+    (P_ij is even because every shell is); order 2 is P_ij(0).  Nothing large is
+    ever rounded, so the result is exact for any count that fits in int64.
+    """
+    tuples = np.asarray(tuples, dtype=np.int64)
+    order = tuples.shape[1]
+    if order not in (2, 3, 4):
+        raise ValueError("polygon_counts_exact supports orders 2, 3 and 4")
+    wz = np.full(N // 2 + 1, 2, dtype=np.int64)      # half-spectrum multiplicity of q_z
+    wz[0] = 1
+    wz[N // 2] = 1
+    paired = sorted({int(s) for s in tuples[:, :2].ravel()} |
+                    ({int(s) for s in tuples[:, 2:].ravel()} if order == 4 else set()))
+    c = dict(zip(paired, count_fields(N, n_shells, width, paired)))
+    sid = shell_id_grid(N, n_shells, width) if order == 3 else None
+    cache = {}
+
+    def P(i, j):
+        key = (min(i, j), max(i, j))
+        if key not in cache:
+            cache[key] = pair_counts(c[key[0]], c[key[1]])
+        return cache[key]
+
+    out = np.empty(len(tuples), dtype=np.int64)
+    for n, t in enumerate(tuples.tolist()):
+        if order == 2:
+            out[n] = P(t[0], t[1])[0, 0, 0]
+        elif order == 3:
+            m = sid == t[2]
+            out[n] = int(np.sum(P(t[0], t[1])[m] * np.broadcast_to(wz, m.shape)[m]))
+        else:
+            out[n] = int(np.sum(P(t[0], t[1]) * P(t[2], t[3]) * wz))
+    return out
 
 
 def physical_factor(order: int, N: int, box_length: float) -> float:

@@ -33,7 +33,7 @@ enum { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 constexpr int kCtrWaves = 16;
 constexpr int kCtrThreads = 64 * kCtrWaves;
 constexpr int kSlots = 14;       // tiles per wave (order 3)
-constexpr int kSlots4 = 12;      // tiles per wave (order 4: B rows formed too)
+constexpr int kSlots4 = 10;      // tiles per wave (order 4: B rows formed too)
 constexpr int kSlotsMax = 16;    // stride of the per-wave slot tables
 constexpr int kKStep = 64;       // grid points per LDS stage (two MFMA K-steps)
 constexpr int kRowStride = 68;   // floats per staged field row (64 + 4 pad)
@@ -383,12 +383,22 @@ constexpr int kCntThreads = 256;
 constexpr int kCntTuples = 4;     // candidate tuples per thread
 constexpr int kCntStage = 32;     // wedge points per LDS stage
 
+// Error-free sum of two doubles: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Partials are (hi, lo) pairs: the sum of each thread's terms carried with the
+// rounding errors of every addition, so that counts near 10^12 (C_t near 10^20)
+// still round to the right integer.
 template <int ORDER>
 __global__ __launch_bounds__(kCntThreads) void counts_wedge(const double* __restrict__ cw, long long nwedge,
                                                             const unsigned char* __restrict__ wmult,
                                                             const int* __restrict__ cand, int n_cand,
                                                             int n_shells, int stages_per_chunk,
-                                                            double* __restrict__ part) {
+                                                            double2* __restrict__ part) {
   extern __shared__ double sc[];  // [n_shells][kCntStage] + weights[kCntStage]
   double* sw = sc + (size_t)n_shells * kCntStage;
   const int chunk = blockIdx.x;
@@ -402,7 +412,7 @@ __global__ __launch_bounds__(kCntThreads) void counts_wedge(const double* __rest
 #pragma unroll
     for (int j = 0; j < ORDER; ++j) sh[u][j] = ok[u] ? cand[t * ORDER + j] : 0;
   }
-  double acc[kCntTuples] = {};
+  double hi[kCntTuples] = {}, lo[kCntTuples] = {};
   const long long p0 = (long long)chunk * stages_per_chunk * kCntStage;
   for (int st = 0; st < stages_per_chunk; ++st) {
     const long long base = p0 + (long long)st * kCntStage;
@@ -423,15 +433,37 @@ __global__ __launch_bounds__(kCntThreads) void counts_wedge(const double* __rest
         double v = w;
 #pragma unroll
         for (int j = 0; j < ORDER; ++j) v *= sc[sh[u][j] * kCntStage + q];
-        acc[u] += v;
+        double s, e;
+        two_sum(hi[u], v, s, e);
+        hi[u] = s;
+        lo[u] += e;
       }
     }
   }
 #pragma unroll
   for (int u = 0; u < kCntTuples; ++u) {
     const int t = (tgrp * kCntTuples + u) * kCntThreads + threadIdx.x;
-    if (ok[u]) part[(size_t)chunk * n_cand + t] = acc[u];
+    if (ok[u]) part[(size_t)chunk * n_cand + t] = make_double2(hi[u], lo[u]);
   }
+}
+
+// tmp[grp][e] = sum of part[c][e] over the chunks c of group grp, as (hi, lo) pairs.
+__global__ void reduce_chunks_dd(const double2* __restrict__ part, double2* __restrict__ tmp, int n_chunks,
+                                 int chunks_per_group, long long n_ent) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int grp = blockIdx.y;
+  if (e >= n_ent) return;
+  const int c0 = grp * chunks_per_group;
+  const int c1 = min(n_chunks, c0 + chunks_per_group);
+  double hi = 0.0, lo = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    const double2 v = part[(size_t)c * n_ent + e];
+    double s, err;
+    two_sum(hi, v.x, s, err);
+    hi = s;
+    lo += err + v.y;
+  }
+  tmp[(size_t)grp * n_ent + e] = make_double2(hi, lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,7 +714,7 @@ hipError_t launch_gather(const double* tmp, int n_groups, long long n_ent, const
 
 hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, const unsigned char* wmult,
                                const int* cand, int n_cand, int n_shells, int stages_per_chunk, int n_chunks,
-                               double* part, hipStream_t st) {
+                               double2* part, hipStream_t st) {
   const int per_grp = kCntThreads * kCntTuples;
   dim3 grid(n_chunks, (n_cand + per_grp - 1) / per_grp);
   const size_t shm = ((size_t)n_shells * kCntStage + kCntStage) * sizeof(double);
@@ -695,6 +727,13 @@ hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, co
   else
     hipLaunchKernelGGL(counts_wedge<4>, grid, dim3(kCntThreads), shm, st, cw, nwedge, wmult, cand, n_cand, n_shells,
                        stages_per_chunk, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_dd(const double2* part, double2* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
+                            hipStream_t st) {
+  dim3 grid((unsigned)((n_ent + 255) / 256), n_groups);
+  hipLaunchKernelGGL(reduce_chunks_dd, grid, dim3(256), 0, st, part, tmp, n_chunks, cpg, n_ent);
   return hipGetLastError();
 }
 

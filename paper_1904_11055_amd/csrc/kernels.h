@@ -51,7 +51,7 @@ struct CtrParams {
 };
 constexpr int kCtrWavesHost = 16;
 constexpr int kSlotsHost = 14;
-constexpr int kSlots4Host = 12;
+constexpr int kSlots4Host = 10;
 constexpr int kSlots2Host = 4;
 constexpr int kSlotsMaxHost = 16;   // per-wave stride of the slot tables
 constexpr int kStagePtsHost = 64;
@@ -70,7 +70,9 @@ hipError_t launch_gather(const double* tmp, int n_groups, long long n_ent, const
                          int prec, double* out, double* raw, int* nonfinite, int batch, hipStream_t st);
 hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, const unsigned char* wmult,
                                const int* cand, int n_cand, int n_shells, int stages_per_chunk, int n_chunks,
-                               double* part, hipStream_t st);
+                               double2* part, hipStream_t st);
+hipError_t launch_reduce_dd(const double2* part, double2* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
+                            hipStream_t st);
 hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
                                   int n_closing, int prec, uint4* W, int batch, hipStream_t st);
 hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,

@@ -373,16 +373,16 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
     const int t = tiles[TileKey{loc[c][0], loc[c][1]}];
     (*ent_of_cand)[c] = t * 256 + tile_entry(loc[c][2], loc[c][3]);
   }
-  // units: runs of tiles sharing the A block
+  // units: runs of tiles sharing the A block, cut into pieces that fit one wave
+  const int cap = n == 2 ? ps::kSlots2Host : n == 3 ? ps::kSlotsHost : ps::kSlots4Host;
   std::vector<std::pair<int, int>> units;  // [first tile, count]
   for (int t = 0; t < id;) {
     int u = t;
     while (u < id && tlist[u].a == tlist[t].a) ++u;
-    units.push_back({t, u - t});
+    for (int f = t; f < u; f += cap) units.push_back({f, std::min(cap, u - f)});
     t = u;
   }
   // greedy: largest units first, onto the least loaded wave with room
-  const int cap = n == 2 ? ps::kSlots2Host : n == 3 ? ps::kSlotsHost : ps::kSlots4Host;
   std::vector<int> order(units.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(),
@@ -518,50 +518,69 @@ polyspec_status compute_counts(polyspec_plan_s* p) {
     const int spc = 64;  // 32-point stages per chunk: 2048 wedge points
     const long long pts_per_chunk = (long long)spc * ps::kCntStageHost;
     const int n_chunks = (int)((nwedge + pts_per_chunk - 1) / pts_per_chunk);
-    if ((st = dev_alloc(p, &part, (size_t)n_chunks * n_cand * sizeof(double))) != POLYSPEC_OK) break;
+    if ((st = dev_alloc(p, &part, (size_t)n_chunks * n_cand * sizeof(double2))) != POLYSPEC_OK) break;
     e = ps::launch_counts_wedge(n, (const double*)cw.p, nwedge, (const unsigned char*)wm_d.p, (const int*)cand_d.p,
-                                (int)n_cand, nb, spc, n_chunks, (double*)part.p, p->stream);
+                                (int)n_cand, nb, spc, n_chunks, (double2*)part.p, p->stream);
     if (e != hipSuccess) {
       st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count contraction: ") + hipGetErrorString(e));
       break;
     }
     const int cpg = 64;
     const int ngr = (n_chunks + cpg - 1) / cpg;
-    if ((st = dev_alloc(p, &tmp, (size_t)ngr * n_cand * sizeof(double))) != POLYSPEC_OK) break;
-    e = ps::launch_reduce_f64((const double*)part.p, (double*)tmp.p, n_chunks, cpg, ngr, (long long)n_cand, 1,
-                              p->stream);
+    if ((st = dev_alloc(p, &tmp, (size_t)ngr * n_cand * sizeof(double2))) != POLYSPEC_OK) break;
+    e = ps::launch_reduce_dd((const double2*)part.p, (double2*)tmp.p, n_chunks, cpg, ngr, (long long)n_cand, p->stream);
     if (e != hipSuccess) {
       st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count reduction: ") + hipGetErrorString(e));
       break;
     }
-    std::vector<double> host((size_t)ngr * n_cand);
-    e = hipMemcpyAsync(host.data(), tmp.p, host.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    std::vector<double2> host((size_t)ngr * n_cand);
+    e = hipMemcpyAsync(host.data(), tmp.p, host.size() * sizeof(double2), hipMemcpyDeviceToHost, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
       st = p->fail(POLYSPEC_ERR_DEVICE, std::string("count readback: ") + hipGetErrorString(e));
       break;
     }
+    // N^3 is a power of two, so (hi, lo) / N^3 is exact and the distance to the
+    // nearest integer is computed without cancellation
     const double N3 = (double)N * N * N;
     p->cand_quot.assign(n_cand, 0.0);
     p->cand_count.assign(n_cand, 0);
+    // Allowed distance to the nearest integer: 1e-3, widened to |q| 2^-46 for
+    // large counts, where the FP64 rounding of the count fields themselves (not of
+    // the sum, which is compensated) reaches 1e-3.  Counts of 2^44 or more would
+    // need a tolerance of 1/4 and are refused.
     double worst = 0.0;
     size_t worst_at = 0;
+    bool too_large = false;
     for (size_t c = 0; c < n_cand; ++c) {
-      double s = 0.0;
-      for (int gi = 0; gi < ngr; ++gi) s += host[(size_t)gi * n_cand + c];
-      const double q = s / N3;
-      const double r = std::rint(q);
-      p->cand_quot[c] = q;
+      double hi = 0.0, lo = 0.0;
+      for (int gi = 0; gi < ngr; ++gi) {
+        const double2 v = host[(size_t)gi * n_cand + c];
+        const double s = hi + v.x;
+        const double bb = s - hi;
+        lo += (hi - (s - bb)) + (v.x - bb) + v.y;
+        hi = s;
+      }
+      const double qh = hi / N3, ql = lo / N3;
+      const double r = std::rint(qh + ql);
+      const double frac = (qh - r) + ql;
+      const double tol = std::max(1e-3, std::ldexp(std::fabs(qh), -46));
+      p->cand_quot[c] = qh + ql;
       p->cand_count[c] = (int64_t)r;
-      if (std::fabs(q - r) > worst) {
-        worst = std::fabs(q - r);
+      if (std::fabs(qh) >= std::ldexp(1.0, 44)) too_large = true;
+      if (std::fabs(frac) / tol > worst) {
+        worst = std::fabs(frac) / tol;
         worst_at = c;
       }
     }
-    if (!(worst < 1e-3)) {
+    if (too_large) {
+      st = p->fail(POLYSPEC_ERR_COUNT_NOT_INTEGRAL, "a polygon count reaches 2^44, beyond exact FP64 recovery");
+      break;
+    }
+    if (!(worst < 1.0)) {
       st = p->fail(POLYSPEC_ERR_COUNT_NOT_INTEGRAL,
                    "polygon count quotient " + std::to_string(p->cand_quot[worst_at]) + " of candidate " +
-                       std::to_string(worst_at) + " is not within 1e-3 of an integer");
+                       std::to_string(worst_at) + " is not within max(1e-3, |q| 2^-46) of an integer");
       break;
     }
   } while (false);

@@ -1,0 +1,166 @@
+"""GPU parity at the full sizes of the benchmark workloads.
+
+At these sizes the FP64 oracle cannot afford every tuple, so each test checks
+  * every polygon count against a size-independent rule (the pair-sum rule:
+    sum_k n(i, j, k) = |S_i||S_j| - [i = j] |S_i| whenever q_i + q_j always lands in
+    a shell), and the integrality margin of every count quotient, and
+  * a sample of tuples (all tuples over a few shells) against the oracle, one by
+    one: counts bit-exact against the oracle's integer pair-count route, B within
+    the precision's tolerance (L2 over the sample).
+The plans use the same launch configuration as bench.py.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[configs] {msg}", file=sys.stderr, flush=True)
+
+
+def _gpu_run(fields, order, nb, width, precision):
+    import torch
+    import paper_1904_11055_amd as ps
+    plan = ps.Plan(fields.shape[-1], order, nb, width, batch=fields.shape[0], precision=precision,
+                   device="cuda:0")
+    plan.shells(torch.from_numpy(fields).to("cuda:0"))
+    B = plan.contract().cpu().numpy()
+    bins, quot = plan.candidates()
+    return plan, B, bins, quot
+
+
+def _pair_sum_check(tuples, counts, N, nb, width):
+    table = {tuple(int(v) for v in t): int(c) for t, c in zip(tuples, counts)}
+    S = O.shell_mode_counts(N, nb, width)
+    n = 0
+    for i in range(1, nb + 1):
+        for j in range(i, nb + 1):
+            if i + j + 1 > nb:
+                continue
+            tot = sum(table.get(tuple(sorted((i, j, k))), 0) for k in range(1, nb + 1))
+            assert tot == S[i - 1] * S[j - 1] - (S[i - 1] if i == j else 0), (i, j)
+            n += 1
+    assert n > 0
+
+
+_ORACLE_CACHE = {}
+
+
+def _sampled_oracle(delta, order, nb, width, shells, tuples):
+    """Exact counts and FP64 B of the given tuples (all shells in `shells`) from the oracle."""
+    key = (delta.shape, float(delta.ravel()[0]), order, nb, width, tuple(shells), tuple(tuples))
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = _sampled_oracle_uncached(delta, order, nb, width, shells, tuples)
+    return _ORACLE_CACHE[key]
+
+
+def _sampled_oracle_uncached(delta, order, nb, width, shells, tuples):
+    N = delta.shape[0]
+    dhat = O.polyspec.rfftn(np.asarray(delta, dtype=np.float64))
+    d = O.shell_fields_from_hat(dhat, N, nb, width, shells)
+    S = O.tuple_product_sums({s: d[n] for n, s in enumerate(shells)}, tuples)
+    n_t = O.polygon_counts_exact(N, order, nb, width, tuples)
+    return n_t, S / (float(N) ** 3 * np.maximum(n_t, 1))
+
+
+def _integral(quot):
+    """Every count quotient within max(1e-3, |q| 2^-46) of an integer (the plan's own bound)."""
+    q = np.asarray(quot, dtype=np.float64)
+    return bool(np.all(np.abs(q - np.rint(q)) < np.maximum(1e-3, np.ldexp(np.abs(q), -46))))
+
+
+def _sample(plan_tuples, order, shells):
+    allowed = set(shells)
+    return [tuple(int(v) for v in t) for t in plan_tuples if set(int(v) for v in t) <= allowed]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4)])
+def test_bispec_256_lognormal(gpu, precision, tol):
+    w = fieldgen.WORKLOADS["bispec_256_lognormal"]
+    say("generating the 256^3 lognormal field")
+    fields = fieldgen.workload_fields("bispec_256_lognormal")
+    plan, B, bins, quot = _gpu_run(fields, 3, w["n_shells"], w["width"], precision)
+    assert _integral(quot)
+    _pair_sum_check(plan.tuples, plan.counts, w["N"], w["n_shells"], w["width"])
+    shells = [1, 2, 7, 19, 20, 38, 39, 40]
+    sample = _sample(plan.tuples, 3, shells)
+    say(f"oracle on {len(sample)} sampled triplets")
+    n_ref, B_ref = _sampled_oracle(fields[0], 3, w["n_shells"], w["width"], shells, sample)
+    idx = {tuple(int(v) for v in t): n for n, t in enumerate(plan.tuples)}
+    sel = [idx[t] for t in sample]
+    assert np.array_equal(plan.counts[sel], n_ref)
+    got = B[0, sel]
+    assert np.linalg.norm(got - B_ref) / np.linalg.norm(B_ref) < tol
+    plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4)])
+def test_trispec_256_lognormal(gpu, precision, tol):
+    w = fieldgen.WORKLOADS["trispec_256_lognormal"]
+    say("generating the 256^3 lognormal field")
+    fields = fieldgen.workload_fields("trispec_256_lognormal")
+    plan, B, bins, quot = _gpu_run(fields, 4, w["n_shells"], w["width"], precision)
+    assert _integral(quot)
+    shells = [1, 2, 3, 12, 23, 24]
+    sample = _sample(plan.tuples, 4, shells)
+    say(f"oracle on {len(sample)} sampled quadrilaterals")
+    n_ref, B_ref = _sampled_oracle(fields[0], 4, w["n_shells"], w["width"], shells, sample)
+    idx = {tuple(int(v) for v in t): n for n, t in enumerate(plan.tuples)}
+    sel = [idx[t] for t in sample]
+    assert np.array_equal(plan.counts[sel], n_ref)
+    assert np.linalg.norm(B[0, sel] - B_ref) / np.linalg.norm(B_ref) < tol
+    plan.close()
+
+
+def test_bispec_grad_128x8(gpu):
+    """Batch of 8 Gaussian fields, loss sum_t (B_t - T_t)^2 with T from a ninth field."""
+    import torch
+    import paper_1904_11055_amd as ps
+    w = fieldgen.WORKLOADS["bispec_grad_128x8"]
+    N, nb, width = w["N"], w["n_shells"], w["width"]
+    say("generating 9 Gaussian 128^3 fields")
+    fields = fieldgen.workload_fields("bispec_grad_128x8")
+    target_field = fieldgen.gaussian_field(N, w["target_seed"]).astype(np.float32).astype(np.float64)
+    T = O.polyspectrum(target_field, 3, nb, width)["B"]
+    plan = ps.Plan(N, 3, nb, width, batch=8, precision=ps.SPLIT_BF16, device="cuda:0")
+    x = torch.from_numpy(fields).to("cuda:0").requires_grad_(True)
+    B = ps.polyspectrum(x, plan)
+    Tt = torch.from_numpy(T).to("cuda:0")[None]
+    loss = ((B - Tt) ** 2).sum()
+    loss.backward()
+    g = x.grad.cpu().numpy()
+    Bh = B.detach().cpu().numpy()
+    for b in (0, 5):   # two of the eight fields against the FP64 oracle
+        say(f"oracle forward + gradient for field {b}")
+        ref = O.polyspectrum(fields[b].astype(np.float64), 3, nb, width, return_fields=True)
+        assert np.array_equal(plan.counts, ref["counts"])
+        assert np.linalg.norm(Bh[b] - ref["B"]) / np.linalg.norm(ref["B"]) < 1e-4
+        gref = O.gradient(fields[b].astype(np.float64), 3, nb, width, 2.0 * (ref["B"] - T), result=ref)
+        assert np.linalg.norm(g[b] - gref) / np.linalg.norm(gref) < 1e-4
+    plan.close()
+
+
+def test_bispec_512_counts_and_sample(gpu):
+    """The benchmark's plan: every count by the pair-sum rule, a tuple sample by the oracle."""
+    w = fieldgen.WORKLOADS["bispec_512_lognormal"]
+    say("generating the 512^3 lognormal field")
+    fields = fieldgen.workload_fields("bispec_512_lognormal")
+    plan, B, bins, quot = _gpu_run(fields, 3, w["n_shells"], w["width"], 1)
+    assert _integral(quot)
+    _pair_sum_check(plan.tuples, plan.counts, w["N"], w["n_shells"], w["width"])
+    shells = [1, 32, 64]
+    sample = _sample(plan.tuples, 3, shells)
+    say(f"oracle on {len(sample)} sampled triplets at 512^3")
+    n_ref, B_ref = _sampled_oracle(fields[0], 3, w["n_shells"], w["width"], shells, sample)
+    idx = {tuple(int(v) for v in t): n for n, t in enumerate(plan.tuples)}
+    sel = [idx[t] for t in sample]
+    assert np.array_equal(plan.counts[sel], n_ref)
+    assert np.linalg.norm(B[0, sel] - B_ref) / np.linalg.norm(B_ref) < 1e-4
+    plan.close()

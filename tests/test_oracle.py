@@ -235,3 +235,56 @@ def test_slab_fields_match_full_fields():
     cpart = O.shell_fields_on_planes(None, N, nb, 1.0, planes, unit=True)
     cfull = O.count_fields(N, nb, 1.0)
     np.testing.assert_allclose(cpart, cfull[:, planes], rtol=0, atol=1e-10 * np.abs(cfull).max())
+
+
+def test_compensated_sums_recover_large_integers():
+    """Chunk sums near 5e19 (a 256^3 quadrilateral count times N^3) add up to the right integer."""
+    from fractions import Fraction
+    N = 256
+    rng = np.random.default_rng(0)
+    n_true = 2930376455268
+    vals = rng.uniform(0.5, 1.5, 4096) * (n_true * N ** 3 / 4096)
+    rest = sum(Fraction(float(v)) for v in vals[:-1])
+    vals[-1] = float(n_true * N ** 3 - rest)     # exact total within half an ulp of vals[-1]
+    exact = rest + Fraction(float(vals[-1]))
+    assert abs(exact / N ** 3 - n_true) < 1e-3
+    hi = np.zeros(1)
+    lo = np.zeros(1)
+    plain = 0.0
+    for v in vals:
+        plain += v
+        s_ = hi + v
+        bb = s_ - hi
+        lo += (hi - (s_ - bb)) + (v - bb)
+        hi = s_
+    assert abs(Fraction(float(hi[0])) + Fraction(float(lo[0])) - exact) < 1e-9 * N ** 3
+    assert O.counts_from_sums((hi, lo), N)[0] == n_true
+    assert abs(Fraction(plain) - exact) / N ** 3 > 1e-3   # the plain FP64 sum would miss
+
+
+def test_compensated_product_sums_match_plain_on_small_grid():
+    N, nb = 32, 6
+    c = O.count_fields(N, nb, 1.0)
+    t = O.candidate_tuples(4, nb, True)
+    plain = O.counts_from_sums(O.product_sums(c, t), N)
+    comp = O.counts_from_sums(O.product_sums(c, t, chunk=1000, compensated=True), N)
+    assert np.array_equal(plain, comp)
+    d = {s + 1: c[s] for s in range(nb)}
+    assert np.array_equal(O.counts_from_sums(O.tuple_product_sums(d, t[:20]), N), plain[:20])
+
+
+@pytest.mark.parametrize("order,nb", [(2, 7), (3, 6), (4, 4)])
+def test_exact_counts_match_direct_enumeration(order, nb):
+    """Aliased 16^3 grid: every sorted tuple, integer pair-count route against brute force."""
+    N = 16
+    t = O.sorted_tuples(order, nb)
+    cnt, _ = O.bruteforce_polyspectrum(np.ones((N, N, N)), order, nb, 1.0, t)
+    assert np.array_equal(O.polygon_counts_exact(N, order, nb, 1.0, t), cnt)
+
+
+@pytest.mark.parametrize("order,nb,width", [(3, 16, 1.0), (4, 10, 1.0), (4, 6, 2.0)])
+def test_exact_counts_match_fft_counts(order, nb, width):
+    N = 64
+    t = O.candidate_tuples(order, nb, O.is_alias_free(N, order, nb, width))
+    assert np.array_equal(O.polygon_counts_exact(N, order, nb, width, t),
+                          O.polygon_counts(N, order, nb, width, t))
