@@ -121,7 +121,7 @@ def outer_radius(n_shells: int, width: float) -> float:
 def is_alias_free(N: int, order: int, n_shells: int, width: float) -> bool:
     """n K_e <= N: no sum of n shell vectors can wrap around the periodic grid.
 
-    Sec. 1 and Sec. 4.2 require a grid of at least (n N_max)^3 for the n-point
+    Sec. 1 and Sec. 4.3 require a grid of at least (n N_max)^3 for the n-point
     function; with the outer edge K_e the exact condition is n K_e <= N.
     """
     return order * Fraction(width) * Fraction(2 * n_shells + 1, 2) <= N
@@ -134,7 +134,7 @@ def shell_mode_counts(N: int, n_shells: int, width: float) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# Tuples (Sec. 4.3: k_1 >= ... >= k_n, flattened row-major with k_n fastest;
+# Tuples (Sec. 4.2: k_1 >= ... >= k_n, flattened row-major with k_n fastest;
 # stored here in the equivalent ascending form t_1 <= ... <= t_n).
 # ----------------------------------------------------------------------------
 def sorted_tuples(order: int, n_shells: int) -> np.ndarray:
@@ -222,7 +222,7 @@ def shell_fields_on_planes(delta_hat: np.ndarray, N: int, n_shells: int, width: 
 
 
 # ----------------------------------------------------------------------------
-# Product sums (Sec. 2: "the matrix inner product" of the shell fields;
+# Product sums (Sec. 2: the grid sum of products of the shell fields;
 # Appendix A: sum over [x] of prod_j FFTW(I~_{k_j})).
 # ----------------------------------------------------------------------------
 def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192, compensated: bool = False):

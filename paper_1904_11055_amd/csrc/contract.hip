@@ -19,10 +19,23 @@
 //   SPLIT_BF16  x = hi + lo (bf16 each), hi*hi + hi*lo + lo*hi with three
 //               v_mfma_f32_16x16x32_bf16, float32 accumulation,
 //   SPLIT_FP16  the same with f16 after a power-of-two scaling of every shell.
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace ps {
+
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1: loop bodies with
+// compile-time indices (static register arrays) without relying on unrolling.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
@@ -177,6 +190,28 @@ __device__ __forceinline__ Operand<PREC> form_pair(const float* S, int uv, int g
   return make_operand<PREC>(x, 1.f);
 }
 
+// FP16 pair product straight from the split operand words of its two shell rows,
+// with packed half-precision error-free products: p_hi = fl(u_hi v_hi), its rounding
+// error e = u_hi v_hi - p_hi exactly (one fused multiply-add), and
+// p_lo = fl(u_hi v_lo + u_lo v_hi + e).  The dropped u_lo v_lo and the rounding of
+// p_lo are both about 2^-22 of the product.  Row r of shell block kb at point group
+// g sits at word [kb][16 g + r % 16] of the operand arrays.
+typedef __attribute__((__vector_size__(2 * sizeof(_Float16)))) _Float16 f16x2;
+__device__ __forceinline__ Operand<kFP16> form_pair_f16(const uint4 (*hi)[64], const uint4 (*lo)[64], int uv,
+                                                        int lane) {
+  const int u = uv & 0xff, v = (uv >> 8) & 0xff;
+  const int iu = (lane & 0x30) | (u & 15), iv = (lane & 0x30) | (v & 15);
+  const f16x8 uh = __builtin_bit_cast(f16x8, hi[u >> 4][iu]);
+  const f16x8 ul = __builtin_bit_cast(f16x8, lo[u >> 4][iu]);
+  const f16x8 vh = __builtin_bit_cast(f16x8, hi[v >> 4][iv]);
+  const f16x8 vl = __builtin_bit_cast(f16x8, lo[v >> 4][iv]);
+  Operand<kFP16> o;
+  o.hi = uh * vh;
+  const f16x8 e = __builtin_elementwise_fma(uh, vh, -o.hi);
+  o.lo = __builtin_elementwise_fma(uh, vl, __builtin_elementwise_fma(ul, vh, e));
+  return o;
+}
+
 // ORDER 2: A = shell block, B = shell block;  ORDER 3: A = pair block, B = shell
 // block;  ORDER 4: A = pair block, B = pair block.
 //
@@ -187,9 +222,13 @@ constexpr int slots_for() { return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : kSlots
 
 template <int PREC, int ORDER>
 __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
-  __shared__ __attribute__((aligned(16))) float stage[2][(kMaxBlk * 16 + 1) * kRowStride];
-  __shared__ uint4 opHi[2][2][kMaxBlk][64];   // [buffer][K-step][shell block][lane]
-  __shared__ uint4 opLo[2][2][kMaxBlk][64];
+  // FP16 forms pair products from the operand words alone; the other precisions
+  // form them from float32 rows staged in `stage`
+  constexpr int kStageFloats = PREC == kFP16 ? 4 : (kMaxBlk * 16 + 1) * kRowStride;
+  __shared__ __attribute__((aligned(16))) float stage[2][kStageFloats];
+  // [buffer][K-step][shell block][lane]; block kMaxBlk stays zero (padding pairs)
+  __shared__ uint4 opHi[2][2][kMaxBlk + 1][64];
+  __shared__ uint4 opLo[2][2][kMaxBlk + 1][64];
   __shared__ float lds_scale[kMaxBlk * 16 + 1];
 
   const int tid = threadIdx.x;
@@ -207,13 +246,15 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
     if (PREC == kFP16) sc = i < p.n_shells ? ldexpf(1.0f, fp16_shell_exp(p.absmax, b * p.n_shells + i)) : 0.f;
     lds_scale[i] = sc;
   }
-  for (int i = tid; i < 2 * (nrows + 1) * kRowStride; i += kCtrThreads) {
-    const int buf = i / ((nrows + 1) * kRowStride);
-    const int rr = (i / kRowStride) % (nrows + 1);
-    if (rr >= p.n_shells) stage[buf][i % ((nrows + 1) * kRowStride)] = 0.f;
+  if constexpr (PREC != kFP16) {
+    for (int i = tid; i < 2 * (nrows + 1) * kRowStride; i += kCtrThreads) {
+      const int buf = i / ((nrows + 1) * kRowStride);
+      const int rr = (i / kRowStride) % (nrows + 1);
+      if (rr >= p.n_shells) stage[buf][i % ((nrows + 1) * kRowStride)] = 0.f;
+    }
   }
-  for (int i = tid; i < 4 * kMaxBlk * 64; i += kCtrThreads) {
-    const int bh = i / (kMaxBlk * 64), kb = (i / 64) % kMaxBlk, ln = i % 64;
+  for (int i = tid; i < 4 * (kMaxBlk + 1) * 64; i += kCtrThreads) {
+    const int bh = i / ((kMaxBlk + 1) * 64), kb = (i / 64) % (kMaxBlk + 1), ln = i % 64;
     if (kb * 16 + (ln & 15) >= p.n_shells) {
       opHi[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
       opLo[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
@@ -240,7 +281,7 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
       const float sc = lds_scale[st_row];
       v = make_float4(v.x * sc, v.y * sc, v.z * sc, v.w * sc);
     }
-    *reinterpret_cast<float4*>(&stage[buf][st_row * kRowStride + st_col]) = v;
+    if constexpr (PREC != kFP16) *reinterpret_cast<float4*>(&stage[buf][st_row * kRowStride + st_col]) = v;
     if constexpr (PREC == kFP32) {
       const uint4 w = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
                                  __float_as_uint(v.w));
@@ -290,11 +331,13 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
           A = op_from_words<PREC>(opHi[cur][h][ab][lane], opLo[cur][h][ab][lane]);
         } else if (info & 0x10) {
           const int uv = ORDER == 3 ? (lv[s / 2] >> (16 * (s % 2))) & 0xffff : lv[s] & 0xffff;
-          A = form_pair<PREC>(S + 32 * h, uv, g);
+          if constexpr (PREC == kFP16) A = form_pair_f16(opHi[cur][h], opLo[cur][h], uv, lane);
+          else A = form_pair<PREC>(S + 32 * h, uv, g);
         }
         Operand<PREC> Bop;
         if (ORDER == 4) {
-          Bop = form_pair<PREC>(S + 32 * h, (lv[s] >> 16) & 0xffff, g);
+          if constexpr (PREC == kFP16) Bop = form_pair_f16(opHi[cur][h], opLo[cur][h], (lv[s] >> 16) & 0xffff, lane);
+          else Bop = form_pair<PREC>(S + 32 * h, (lv[s] >> 16) & 0xffff, g);
         } else {
           const int bb = info & 3;
           Bop = op_from_words<PREC>(opHi[cur][h][bb][lane], opLo[cur][h][bb][lane]);
@@ -314,6 +357,168 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
     if ((un[s / 4] >> (8 * (s % 4))) & 0x80) break;
     const int t = my_tiles[s];
     *reinterpret_cast<f32x4*>(out + (size_t)t * 256 + 4 * lane) = acc[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Order 3, pair blocks aligned to shell blocks (FP16 split).
+//   S[(i, j), k] = sum_x d_i d_j d_k  for i in shell block ib, one shell j, k in block kb.
+// For j in the first two shell blocks the A operand of tile (ib, j, kb) is the
+// shell-block operand of ib times the row of shell j (the same for all 16 rows); for
+// j in the last two, where fewer blocks kb >= jb than ib <= jb exist, the B operand
+// of kb is scaled by d_j instead.  Either way every operand of a 32-point step comes
+// from the four shell-block operands held in registers plus two LDS reads per j (all
+// 16 rows of a point group read one word).  Wave w owns j = w + 8 q and the
+// tiles (ib <= jb = q / 2, kb >= jb), one static accumulator each; a per-wave mask
+// says which of them hold a candidate tuple.  Rows i > j of the diagonal block are
+// computed and never read.
+// ---------------------------------------------------------------------------
+constexpr int kJThreads = 64 * kJWaves;
+static_assert(jslot(7, 3, 3) + 1 == kJSlots, "slot numbering");
+
+__device__ __forceinline__ Operand<kFP16> pair_f16(const Operand<kFP16>& a, const Operand<kFP16>& b) {
+  Operand<kFP16> o;
+  o.hi = a.hi * b.hi;
+  const f16x8 e = __builtin_elementwise_fma(a.hi, b.hi, -o.hi);
+  o.lo = __builtin_elementwise_fma(a.hi, b.lo, __builtin_elementwise_fma(a.lo, b.hi, e));
+  return o;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kJThreads, 1) void contract_j3(CtrJParams p) {
+  static_assert(PREC == kFP16, "shell-block aligned contraction is implemented for the FP16 split");
+  __shared__ uint4 opHi[2][2][kMaxBlk][64];   // [buffer][K-step][shell block][lane]
+  __shared__ uint4 opLo[2][2][kMaxBlk][64];
+  __shared__ float lds_scale[kMaxBlk * 16];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int chunk = blockIdx.x;
+  const int b = blockIdx.z;
+
+  for (int i = tid; i < kMaxBlk * 16; i += kJThreads)
+    lds_scale[i] = i < p.n_shells ? ldexpf(1.0f, fp16_shell_exp(p.absmax, b * p.n_shells + i)) : 0.f;
+  for (int i = tid; i < 4 * kMaxBlk * 64; i += kJThreads) {
+    const int bh = i / (kMaxBlk * 64), kb = (i / 64) % kMaxBlk, ln = i % 64;
+    if (kb * 16 + (ln & 15) >= p.n_shells) {
+      opHi[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
+      opLo[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+
+  // staging: float4 #f of the (64 shells x 64 points) slice, f = tid and tid + kJThreads
+  const float* Db = p.D + (size_t)b * p.n_shells * p.G;
+  const long long x_base = (long long)chunk * p.ksteps * kKStep;
+  constexpr int kF4 = 64 * kKStep / 4 / kJThreads;   // float4 per thread per stage
+  int st_row[kF4], st_col[kF4];
+#pragma unroll
+  for (int f = 0; f < kF4; ++f) {
+    const int idx = tid + f * kJThreads;
+    st_row[f] = idx >> 4;
+    st_col[f] = (idx & 15) * 4;
+  }
+  auto stage_store = [&](int buf, int f, float4 v) {
+    const int row = st_row[f], col = st_col[f];
+    const float sc = lds_scale[row];
+    v = make_float4(v.x * sc, v.y * sc, v.z * sc, v.w * sc);
+    uint2 hi, lo;
+    split4<PREC>(v, 1.f, hi, lo);
+    const int h = col >> 5, kb = row >> 4, ln = (((col & 31) >> 3) << 4) | (row & 15), half = (col >> 2) & 1;
+    reinterpret_cast<uint2*>(&opHi[buf][h][kb][ln])[half] = hi;
+    reinterpret_cast<uint2*>(&opLo[buf][h][kb][ln])[half] = lo;
+  };
+  float4 pre[kF4];
+#pragma unroll
+  for (int f = 0; f < kF4; ++f) {
+    pre[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (st_row[f] < p.n_shells)
+      pre[f] = *reinterpret_cast<const float4*>(Db + (size_t)st_row[f] * p.G + x_base + st_col[f]);
+  }
+#pragma unroll
+  for (int f = 0; f < kF4; ++f)
+    if (st_row[f] < p.n_shells) stage_store(0, f, pre[f]);
+  __syncthreads();
+
+  const unsigned m0 = __builtin_amdgcn_readfirstlane(p.slot_mask[2 * wave]);
+  const unsigned m1 = __builtin_amdgcn_readfirstlane(p.slot_mask[2 * wave + 1]);
+  f32x4 acc[kJSlots];
+#pragma unroll
+  for (int s = 0; s < kJSlots; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ks = 0; ks < p.ksteps; ++ks) {
+    const int cur = ks & 1;
+    if (ks + 1 < p.ksteps) {
+#pragma unroll
+      for (int f = 0; f < kF4; ++f)
+        if (st_row[f] < p.n_shells)
+          pre[f] = *reinterpret_cast<const float4*>(Db + (size_t)st_row[f] * p.G + x_base + (ks + 1) * kKStep +
+                                                    st_col[f]);
+    }
+    // the slot masks are re-read from SGPRs every step (scalar bit tests) instead of
+    // being kept as 40 precomputed lane masks, which would not fit in the SGPRs
+    unsigned mm0 = m0, mm1 = m1;
+    asm volatile("" : "+s"(mm0), "+s"(mm1));
+    mm0 = __builtin_amdgcn_readfirstlane(mm0);
+    mm1 = __builtin_amdgcn_readfirstlane(mm1);
+    auto active = [&](int s) { return ((s < 32 ? mm0 >> s : mm1 >> (s - 32)) & 1u) != 0; };
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      Operand<PREC> Bop[kMaxBlk];
+#pragma unroll
+      for (int kb = 0; kb < kMaxBlk; ++kb) Bop[kb] = op_from_words<PREC>(opHi[cur][h][kb][lane], opLo[cur][h][kb][lane]);
+      static_for<8>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int jb = q / 2;
+        const int j = wave + kJWaves * q;
+        if (j >= p.n_shells) return;
+        const int rj = (lane & 0x30) | (j & 15);
+        const Operand<PREC> dj = op_from_words<PREC>(opHi[cur][h][jb][rj], opLo[cur][h][jb][rj]);
+        if constexpr (jb <= 1) {
+          // few blocks ib <= jb: scale the A side, A = (d_i d_j) rows
+          static_for<jb + 1>([&](auto ibc) {
+            constexpr int ib = decltype(ibc)::value;
+            bool any = false;
+            static_for<kMaxBlk - jb>([&](auto kc) { any = any || active(jslot(q, ib, jb + decltype(kc)::value)); });
+            if (!any) return;
+            const Operand<PREC> A = pair_f16(Bop[ib], dj);
+            static_for<kMaxBlk - jb>([&](auto kc) {
+              constexpr int kb = jb + decltype(kc)::value;
+              if (active(jslot(q, ib, kb))) mma<PREC>(acc[jslot(q, ib, kb)], A, Bop[kb]);
+            });
+          });
+        } else {
+          // few blocks kb >= jb: scale the B side, B = (d_j d_k) columns; same sums
+          static_for<kMaxBlk - jb>([&](auto kc) {
+            constexpr int kb = jb + decltype(kc)::value;
+            bool any = false;
+            static_for<jb + 1>([&](auto ibc) { any = any || active(jslot(q, decltype(ibc)::value, kb)); });
+            if (!any) return;
+            const Operand<PREC> Bs = pair_f16(Bop[kb], dj);
+            static_for<jb + 1>([&](auto ibc) {
+              constexpr int ib = decltype(ibc)::value;
+              if (active(jslot(q, ib, kb))) mma<PREC>(acc[jslot(q, ib, kb)], Bop[ib], Bs);
+            });
+          });
+        }
+      });
+    }
+    if (ks + 1 < p.ksteps) {
+#pragma unroll
+      for (int f = 0; f < kF4; ++f)
+        if (st_row[f] < p.n_shells) stage_store(cur ^ 1, f, pre[f]);
+    }
+    __syncthreads();
+  }
+
+  auto active = [&](int s) { return ((s < 32 ? m0 >> s : m1 >> (s - 32)) & 1u) != 0; };
+  const int* my_tiles = p.tile_of_slot + wave * kJSlots;
+  float* out = p.partials + ((size_t)b * p.n_chunks + chunk) * (size_t)p.n_tiles * 256;
+#pragma unroll
+  for (int s = 0; s < kJSlots; ++s) {
+    if (!active(s)) continue;
+    *reinterpret_cast<f32x4*>(out + (size_t)my_tiles[s] * 256 + 4 * lane) = acc[s];
   }
 }
 
@@ -551,123 +756,147 @@ __device__ __forceinline__ float operand_value(const Operand<PREC>& o, int r) {
 }
 
 // a_m[x] = sum_v d_v[x] Y_v[m][x],  Y_v[m][x] = sum_{u <= v} W[m][(u, v)] d_u[x].
-// A workgroup of 16 waves owns 512 grid points (32 per wave) and every shell m.  The
-// B operands (the fields d_u at the wave's points, 4 chunks of 16 shells) are built
-// once and stay in registers; d_v is read back from them.  The weight operands of
-// kAdjVG values of v at a time are staged in LDS (double buffered, reusing the LDS
-// that held the fields) and shared by all waves.
-constexpr int kAdjWaves = 16;
-constexpr int kAdjPts = 32 * kAdjWaves;
-constexpr int kAdjStride = kAdjPts + 1;
+// A workgroup of 8 waves owns 512 grid points, each wave two 32-point column blocks,
+// and every shell m.  The B operands (the fields d_u at the wave's points, 4 chunks
+// of 16 shells per column block) are loaded once from HBM straight into registers;
+// d_v is read back from them.  The weight operands of kAdjVG values of v at a time
+// are staged in LDS, double buffered: while one stage is in use the next one is
+// copied in, a piece per v, with one barrier per stage.  Each weight block read
+// from LDS feeds both column blocks (two independent MFMA chains).
+constexpr int kAdjWaves = 8;
+constexpr int kAdjPB = 2;                                   // 32-point column blocks per wave
+constexpr int kAdjThreads = 64 * kAdjWaves;
+constexpr int kAdjPts = 32 * kAdjPB * kAdjWaves;
 constexpr int kAdjVG = 4;
-constexpr int kAdjWPerV = 4 * kAdjMaxMb * 2 * 64;   // uint4 words of W per v
-constexpr size_t kAdjLdsBytes = (size_t)(kAdjMaxMb * 32 + 1) * kAdjStride * 4;
-static_assert(2 * kAdjVG * kAdjWPerV * 16 <= kAdjLdsBytes, "weight stage must fit in the field buffer");
+constexpr int kAdjWPerV = 4 * kAdjMaxMb * 2 * 64;           // uint4 words of W per v
+constexpr int kAdjStageWords = kAdjVG * kAdjWPerV;
+constexpr int kAdjPiece = kAdjWPerV / kAdjThreads;          // words per thread per v step
+static_assert(kAdjPiece * kAdjThreads == kAdjWPerV, "a stage is copied in kAdjVG equal pieces");
 
 template <int PREC>
-__global__ __launch_bounds__(64 * kAdjWaves, 1) void adjoint_gemm(const float* __restrict__ D,
-                                                                  const uint4* __restrict__ W,
-                                                                  const int* __restrict__ vmask, int n_shells,
-                                                                  long long G, float* __restrict__ A) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kAdjLdsBytes];
-  float* fld = reinterpret_cast<float*>(lds);
-  uint4* wst = reinterpret_cast<uint4*>(lds);   // [2][kAdjVG][kAdjWPerV] after the fields are consumed
+__global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __restrict__ D,
+                                                             const uint4* __restrict__ W,
+                                                             const int* __restrict__ vmask, int n_shells,
+                                                             long long G, float* __restrict__ A) {
+  __shared__ uint4 wst[2][kAdjStageWords];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int hh = lane >> 5, col = lane & 31;
   const int b = blockIdx.y;
-  const long long x0 = (long long)blockIdx.x * kAdjPts;
+  const long long xw = (long long)blockIdx.x * kAdjPts + wave * 32 * kAdjPB + col;
   const float* Db = D + (size_t)b * n_shells * G;
-  for (int i = tid; i < 64 * kAdjPts; i += 64 * kAdjWaves) {
-    const int s = i / kAdjPts, q = i % kAdjPts;
-    fld[s * kAdjStride + q] = (s < n_shells) ? Db[(size_t)s * G + x0 + q] : 0.f;
-  }
-  __syncthreads();
-  const int pt = wave * 32 + col;
-  Operand<PREC> Bu[4];
+
+  // B operands: lane (hh, col) holds shells 16 uc + 8 hh + r at point col of block pb
+  Operand<PREC> Bu[kAdjPB][4];
 #pragma unroll
-  for (int uc = 0; uc < 4; ++uc) {
-    float x[8];
+  for (int pb = 0; pb < kAdjPB; ++pb) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) x[r] = fld[(16 * uc + 8 * hh + r) * kAdjStride + pt];
-    Bu[uc] = make_operand<PREC>(x, 1.f);
+    for (int uc = 0; uc < 4; ++uc) {
+      float x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int sh = 16 * uc + 8 * hh + r;
+        x[r] = sh < n_shells ? Db[(size_t)sh * G + xw + 32 * pb] : 0.f;
+      }
+      Bu[pb][uc] = make_operand<PREC>(x, 1.f);
+    }
   }
-  __syncthreads();   // the field buffer becomes the weight stage
 
   const uint4* Wb = W + (size_t)b * n_shells * kAdjWPerV;
   const int n_stages = (n_shells + kAdjVG - 1) / kAdjVG;
-  constexpr int kPerThread = kAdjVG * kAdjWPerV / (64 * kAdjWaves);
-  uint4 wpre[kPerThread];
-  auto w_fetch = [&](int stage) {
+  uint4 wp[kAdjPiece];
+  // piece q of stage s: words (q kAdjPiece + k) kAdjThreads + tid of the stage
+  auto w_load = [&](int s, int q) {
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-      const int i = tid + k * 64 * kAdjWaves;
-      const int v = stage * kAdjVG + i / kAdjWPerV;
-      wpre[k] = v < n_shells ? Wb[(size_t)v * kAdjWPerV + i % kAdjWPerV] : make_uint4(0, 0, 0, 0);
+    for (int k = 0; k < kAdjPiece; ++k) {
+      const int i = (q * kAdjPiece + k) * kAdjThreads + tid;
+      const int v = s * kAdjVG + i / kAdjWPerV;
+      wp[k] = v < n_shells ? Wb[(size_t)s * kAdjStageWords + i] : make_uint4(0, 0, 0, 0);
     }
   };
-  auto w_store = [&](int buf) {
+  auto w_store = [&](int buf, int q) {
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) wst[buf * kAdjVG * kAdjWPerV + tid + k * 64 * kAdjWaves] = wpre[k];
+    for (int k = 0; k < kAdjPiece; ++k) wst[buf][(q * kAdjPiece + k) * kAdjThreads + tid] = wp[k];
   };
-  w_fetch(0);
-  w_store(0);
+  for (int q = 0; q < kAdjVG; ++q) {
+    w_load(0, q);
+    w_store(0, q);
+  }
   __syncthreads();
 
-  f32x16 acc[kAdjMaxMb];
+  f32x16 acc[kAdjPB][kAdjMaxMb];
 #pragma unroll
-  for (int mb = 0; mb < kAdjMaxMb; ++mb)
+  for (int pb = 0; pb < kAdjPB; ++pb)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[mb][i] = 0.f;
+    for (int mb = 0; mb < kAdjMaxMb; ++mb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[pb][mb][i] = 0.f;
 
 #pragma unroll
   for (int vc = 0; vc < 4; ++vc) {            // fully unrolled: register indices stay static
     if (16 * vc >= n_shells) break;
-    const Operand<PREC>& Bv = Bu[vc];
 #pragma unroll
     for (int vv = 0; vv < 16; ++vv) {
       const int v = 16 * vc + vv;
       if (v >= n_shells) break;
       const int st = v / kAdjVG, vi = v % kAdjVG;
-      if (vi == 0 && st + 1 < n_stages) w_fetch(st + 1);
+      const bool more = st + 1 < n_stages;
+      if (more) {                 // copy the next stage in, one piece per v
+        if (vi > 0) w_store((st + 1) & 1, vi - 1);
+        w_load(st + 1, vi);
+      }
       const int mask = __builtin_amdgcn_readfirstlane(vmask[v]);   // bit 2 uc + mb
-      const uint4* wv = wst + ((st & 1) * kAdjVG + vi) * kAdjWPerV;
-      // d_v at this lane's point: element vv % 8 of chunk vc, held by the half vv / 8
-      const float own = operand_value<PREC>(Bv, vv % 8);
-      const float other = __shfl_xor(own, 32);
-      const float dv = (hh == vv / 8) ? own : other;
+      const uint4* wv = wst[st & 1] + vi * kAdjWPerV;
+      // d_v at this lane's points: element vv % 8 of chunk vc, held by the half vv / 8
+      float dv[kAdjPB];
+#pragma unroll
+      for (int pb = 0; pb < kAdjPB; ++pb) {
+        const float own = operand_value<PREC>(Bu[pb][vc], vv % 8);
+        const float other = __shfl_xor(own, 32);
+        dv[pb] = (hh == vv / 8) ? own : other;
+      }
 #pragma unroll
       for (int mb = 0; mb < kAdjMaxMb; ++mb) {
         if (!(mask & (0x55 << mb))) continue;   // no weight in this shell block of m
-        f32x16 Y;
+        Operand<PREC> Wop[4];
 #pragma unroll
         for (int uc = 0; uc <= vc; ++uc) {
           const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
-          const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
-          if (uc == 0) mma32_first<PREC>(Y, Wop, Bu[0]);
-          else mma32<PREC>(Y, Wop, Bu[uc]);
+          Wop[uc] = op_from_words<PREC>(blk[lane], blk[64 + lane]);
+        }
+        f32x16 Y[kAdjPB];
+#pragma unroll
+        for (int uc = 0; uc <= vc; ++uc) {
+#pragma unroll
+          for (int pb = 0; pb < kAdjPB; ++pb) {
+            if (uc == 0) mma32_first<PREC>(Y[pb], Wop[uc], Bu[pb][uc]);
+            else mma32<PREC>(Y[pb], Wop[uc], Bu[pb][uc]);
+          }
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[mb][i] += dv * Y[i];
+        for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[pb][mb][i] += dv[pb] * Y[pb][i];
       }
-      if (vi == kAdjVG - 1 || v + 1 == n_shells) {
-        if (st + 1 < n_stages) {
-          __syncthreads();          // every wave is done with the other buffer
-          w_store((st + 1) & 1);
-          __syncthreads();
-        }
+      if (more && (vi == kAdjVG - 1)) {
+        w_store((st + 1) & 1, kAdjVG - 1);
+        __syncthreads();          // the next stage is complete; this one is free
       }
     }
   }
-  // acc[mb]: lane l, register i -> row m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4, point l % 32
-  float* Ab = A + (size_t)b * n_shells * G + x0 + pt;
+  // acc[pb][mb]: lane l, register i -> row m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4,
+  // point l % 32 of column block pb
+  float* Ab = A + (size_t)b * n_shells * G + xw;
 #pragma unroll
-  for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+  for (int pb = 0; pb < kAdjPB; ++pb) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
-      if (m < n_shells) Ab[(size_t)m * G] = acc[mb][i];
+    for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+        if (m < n_shells) Ab[(size_t)m * G + 32 * pb] = acc[pb][mb][i];
+      }
     }
   }
 }
@@ -686,6 +915,13 @@ hipError_t launch_contract(int prec, int order, const CtrParams& p, int n_groups
     if (prec == kFP32) L(kFP32, 4); else if (prec == kBF16) L(kBF16, 4); else L(kFP16, 4);
   }
 #undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_j3(int prec, const CtrJParams& p, int batch, hipStream_t st) {
+  if (prec != kFP16) return hipErrorInvalidValue;
+  dim3 grid(p.n_chunks, 1, batch);
+  hipLaunchKernelGGL(contract_j3<kFP16>, grid, dim3(kJThreads), 0, st, p);
   return hipGetLastError();
 }
 
@@ -748,9 +984,9 @@ hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const i
                                float* A, int batch, hipStream_t st) {
   dim3 grid((unsigned)(G / kAdjPts), batch);
   if (prec == kFP32)
-    hipLaunchKernelGGL(adjoint_gemm<kFP32>, grid, dim3(64 * kAdjWaves), 0, st, D, W, vmask, n_shells, G, A);
+    hipLaunchKernelGGL(adjoint_gemm<kFP32>, grid, dim3(kAdjThreads), 0, st, D, W, vmask, n_shells, G, A);
   else
-    hipLaunchKernelGGL(adjoint_gemm<kBF16>, grid, dim3(64 * kAdjWaves), 0, st, D, W, vmask, n_shells, G, A);
+    hipLaunchKernelGGL(adjoint_gemm<kBF16>, grid, dim3(kAdjThreads), 0, st, D, W, vmask, n_shells, G, A);
   return hipGetLastError();
 }
 

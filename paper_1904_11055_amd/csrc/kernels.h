@@ -61,6 +61,31 @@ constexpr int kCntTuplesPerGroup = 1024;
 constexpr int kCntStageHost = 32;
 
 hipError_t launch_contract(int prec, int order, const CtrParams& p, int n_groups, int batch, hipStream_t st);
+
+// Order 3 with pair blocks aligned to shell blocks: wave w of kJWaves owns the shells
+// j = w + kJWaves q (q = 0..7, shell block jb = q / 2) and the tiles (ib <= jb, kb >= jb)
+// of each, at most kJSlots per wave, numbered by jslot().
+constexpr int kJWaves = 8;
+constexpr int kJSlots = 40;
+__host__ __device__ constexpr int jslot(int q, int ib, int kb) {
+  int s = 0;
+  for (int qq = 0; qq < q; ++qq) s += (qq / 2 + 1) * (4 - qq / 2);
+  return s + ib * (4 - q / 2) + (kb - q / 2);
+}
+struct CtrJParams {
+  const float* D;
+  const unsigned* absmax;
+  const int* tile_of_slot;   // [kJWaves][kJSlots]: compact tile id, or -1
+  const unsigned* slot_mask; // [kJWaves][2]: bit s set when slot s holds a tile
+  float* partials;
+  long long G;
+  int n_shells;
+  int n_blk;
+  int n_tiles;
+  int ksteps;
+  int n_chunks;
+};
+hipError_t launch_contract_j3(int prec, const CtrJParams& p, int batch, hipStream_t st);
 hipError_t launch_reduce_f32(const float* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
                              int batch, hipStream_t st);
 hipError_t launch_reduce_f64(const double* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,

@@ -92,9 +92,13 @@ struct polyspec_plan_s {
   int red_groups = 0, red_cpg = 0;
   int n_adj_active = 0;
   std::vector<int> pair_uv;
+  // shell-block aligned order-3 schedule (FP16 split)
+  bool jsched = false;
+  int n_tiles_j = 0, ksteps_j = 0, n_chunks_j = 0;
 
   // device tables
   DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_lane_d, slot_tile_d, ent_d, bins_d, fnorm_d, lookup_d, wmask_d, flag_d;
+  DevBuf jtile_d, jmask_d, ent_j_d;
   // workspace carving
   DevBuf own_ws;
   char* ws = nullptr;
@@ -251,8 +255,9 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   L.H2 = align256(zf * p->N * p->N * p->B2 * sizeof(cplx<float>));
   L.D = align256(zf * (size_t)p->G * sizeof(float));
   L.A = (p->order == 3) ? L.D : 0;
-  L.partials = align256((size_t)p->batch * p->n_chunks * (size_t)p->n_tiles * 256 * sizeof(float));
-  L.red = align256((size_t)p->batch * p->red_groups * (size_t)p->n_tiles * 256 * sizeof(double));
+  const size_t tiles = (size_t)std::max(p->n_tiles, p->n_tiles_j);
+  L.partials = align256((size_t)p->batch * p->n_chunks * tiles * 256 * sizeof(float));
+  L.red = align256((size_t)p->batch * p->red_groups * tiles * 256 * sizeof(double));
   L.absmax = align256(zf * sizeof(unsigned)) + align256(zf * ps::kAbsmaxSpreadHost * sizeof(unsigned));
   L.W = (p->order == 3) ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16) : 0;
   L.total = L.box + L.gbox + L.H1 + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
@@ -453,6 +458,37 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
   return POLYSPEC_OK;
 }
 
+// Order 3, shell-block aligned schedule: candidate (i <= j <= k) lives in slot
+// jslot(j / 8, i / 16, k / 16) of wave j % 8; used slots get compact tile ids.
+polyspec_status build_jsched(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
+  p->jsched = p->order == 3 && p->n_blk <= ps::kMaxBlkHost;
+  if (!p->jsched) return POLYSPEC_OK;
+  const size_t nc = p->cand.size() / 3;
+  std::vector<int> tile((size_t)ps::kJWaves * ps::kJSlots, -1);
+  std::vector<unsigned> mask((size_t)ps::kJWaves * 2, 0u);
+  auto slot_of = [&](const int* t) {
+    return (t[1] % ps::kJWaves) * ps::kJSlots + ps::jslot(t[1] / ps::kJWaves, t[0] / 16, t[2] / 16);
+  };
+  for (size_t c = 0; c < nc; ++c) tile[slot_of(&p->cand[c * 3])] = 0;
+  int id = 0;
+  for (int w = 0; w < ps::kJWaves; ++w)
+    for (int s = 0; s < ps::kJSlots; ++s) {
+      int& t = tile[(size_t)w * ps::kJSlots + s];
+      if (t < 0) continue;
+      t = id++;
+      mask[2 * w + s / 32] |= 1u << (s % 32);
+    }
+  p->n_tiles_j = id;
+  ent_of_cand->resize(nc);
+  for (size_t c = 0; c < nc; ++c) {
+    const int* t = &p->cand[c * 3];
+    (*ent_of_cand)[c] = tile[slot_of(t)] * 256 + tile_entry(t[0] % 16, t[2] % 16);
+  }
+  PS_TRY(upload(p, &p->jtile_d, tile));
+  PS_TRY(upload(p, &p->jmask_d, mask));
+  return POLYSPEC_OK;
+}
+
 // Plan-time counts: unit-shell fields in float64 on the symmetry wedge, then
 // C_t = sum over the wedge of orbit size times the product.
 polyspec_status compute_counts(polyspec_plan_s* p) {
@@ -650,6 +686,8 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   build_tuples(p);
   std::vector<int> ent_of_cand;
   PS_TRY(build_tiles(p, &ent_of_cand));
+  std::vector<int> ent_j_of_cand;
+  PS_TRY(build_jsched(p, &ent_j_of_cand));
 
   // chunking of the grid for the contraction
   const long long steps = p->G / ps::kStagePtsHost;
@@ -658,6 +696,11 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   while (steps % ks) --ks;
   p->ksteps = (int)ks;
   p->n_chunks = (int)(steps / ks);
+  // the shell-block aligned kernel works on whole 256-point stages
+  long long ksj = std::max(4LL, ks);
+  while (steps % ksj) ++ksj;
+  p->ksteps_j = (int)ksj;
+  p->n_chunks_j = (int)(steps / ksj);
   p->red_cpg = 64;
   p->red_groups = (p->n_chunks + p->red_cpg - 1) / p->red_cpg;
 
@@ -667,7 +710,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   PS_TRY(compute_counts(p));
 
   const size_t nc = p->cand.size() / p->order;
-  std::vector<int> ent;
+  std::vector<int> ent, ent_j;
   std::vector<double> fnorm;
   const double N3 = (double)p->N * p->N * p->N;
   double phys = 1.0;
@@ -684,6 +727,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     for (int j = 0; j < p->order; ++j) p->cl_bins.push_back(p->cand[c * p->order + j]);
     p->cl_counts.push_back(p->cand_count[c]);
     ent.push_back(ent_of_cand[c]);
+    if (p->jsched) ent_j.push_back(ent_j_of_cand[c]);
     fnorm.push_back(phys / (N3 * (double)p->cand_count[c]));
     if (p->order == 3) {
       const int* t = &p->cand[c * 3];
@@ -691,6 +735,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     }
   }
   PS_TRY(upload(p, &p->ent_d, ent));
+  if (p->jsched) PS_TRY(upload(p, &p->ent_j_d, ent_j));
   PS_TRY(upload(p, &p->bins_d, p->cl_bins));
   PS_TRY(upload(p, &p->fnorm_d, fnorm));
   PS_TRY(dev_alloc(p, &p->flag_d, 256));
@@ -721,7 +766,8 @@ void release(polyspec_plan_s* p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   p->ev_pool.clear();
   DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_lane_d, &p->slot_tile_d, &p->ent_d,
-                    &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->own_ws};
+                    &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->jtile_d, &p->jmask_d,
+                    &p->ent_j_d, &p->own_ws};
   for (DevBuf* b : bufs) dev_free(b);
 }
 
@@ -837,6 +883,29 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   return POLYSPEC_OK;
 }
 
+// FP64 reduction of the contraction's partial tiles, then normalisation and gather.
+static polyspec_status finish_contract(polyspec_plan_t p, long long n_ent, int n_chunks, const int* ent,
+                                       double* d_out, double* d_raw_sums) {
+  hipStream_t st = p->stream;
+  // chunk groups of red_cpg chunks; the aligned kernel has at most as many chunks
+  const int groups = (n_chunks + p->red_cpg - 1) / p->red_cpg;
+  PS_TIMED(p, POLYSPEC_PH_REDUCE, ps::launch_reduce_f32(p->partials, p->red, n_chunks, p->red_cpg, groups, n_ent, p->batch, st));
+  const bool guard = p->desc.flags & POLYSPEC_NAN_GUARD;
+  if (guard) PS_HIP(p, ps::launch_fill_u32(p->flag_d.p, 0u, 1, st));
+  const int ncl = (int)p->closing.size();
+  if (ncl > 0)
+    PS_TIMED(p, POLYSPEC_PH_GATHER, ps::launch_gather(p->red, groups, n_ent, ent, (const int*)p->bins_d.p,
+                                p->order, (const double*)p->fnorm_d.p, ncl, p->absmax, p->nb, p->prec, d_out,
+                                d_raw_sums, guard ? (int*)p->flag_d.p : nullptr, p->batch, st));
+  if (guard) {
+    int flag = 0;
+    PS_HIP(p, hipMemcpyAsync(&flag, p->flag_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    PS_HIP(p, hipStreamSynchronize(st));
+    if (flag) return p->fail(POLYSPEC_ERR_DEVICE, "non-finite polyspectrum value");
+  }
+  return POLYSPEC_OK;
+}
+
 polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_raw_sums) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
   if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
@@ -848,6 +917,23 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
     PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));
     PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
     p->absmax_valid = true;
+  }
+  if (p->jsched && p->prec == POLYSPEC_SPLIT_FP16 && p->ksteps_j % 4 == 0) {   // whole 256-point stages
+    ps::CtrJParams jp;
+    jp.D = p->D;
+    jp.absmax = p->absmax;
+    jp.tile_of_slot = (const int*)p->jtile_d.p;
+    jp.slot_mask = (const unsigned*)p->jmask_d.p;
+    jp.partials = p->partials;
+    jp.G = p->G;
+    jp.n_shells = p->nb;
+    jp.n_blk = p->n_blk;
+    jp.n_tiles = p->n_tiles_j;
+    jp.ksteps = p->ksteps_j;
+    jp.n_chunks = p->n_chunks_j;
+    PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract_j3(p->prec, jp, p->batch, st));
+    return finish_contract(p, (long long)p->n_tiles_j * 256, p->n_chunks_j, (const int*)p->ent_j_d.p, d_out,
+                           d_raw_sums);
   }
   ps::CtrParams cp;
   cp.D = p->D;
@@ -865,22 +951,7 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   cp.ksteps = p->ksteps;
   cp.n_chunks = p->n_chunks;
   PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
-  const long long n_ent = (long long)p->n_tiles * 256;
-  PS_TIMED(p, POLYSPEC_PH_REDUCE, ps::launch_reduce_f32(p->partials, p->red, p->n_chunks, p->red_cpg, p->red_groups, n_ent, p->batch, st));
-  const bool guard = p->desc.flags & POLYSPEC_NAN_GUARD;
-  if (guard) PS_HIP(p, ps::launch_fill_u32(p->flag_d.p, 0u, 1, st));
-  const int ncl = (int)p->closing.size();
-  if (ncl > 0)
-    PS_TIMED(p, POLYSPEC_PH_GATHER, ps::launch_gather(p->red, p->red_groups, n_ent, (const int*)p->ent_d.p, (const int*)p->bins_d.p,
-                                p->order, (const double*)p->fnorm_d.p, ncl, p->absmax, p->nb, p->prec, d_out,
-                                d_raw_sums, guard ? (int*)p->flag_d.p : nullptr, p->batch, st));
-  if (guard) {
-    int flag = 0;
-    PS_HIP(p, hipMemcpyAsync(&flag, p->flag_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    PS_HIP(p, hipStreamSynchronize(st));
-    if (flag) return p->fail(POLYSPEC_ERR_DEVICE, "non-finite polyspectrum value");
-  }
-  return POLYSPEC_OK;
+  return finish_contract(p, (long long)p->n_tiles * 256, p->n_chunks, (const int*)p->ent_d.p, d_out, d_raw_sums);
 }
 
 polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, float* d_grad_delta) {

@@ -51,6 +51,13 @@ def _pair_sum_check(tuples, counts, N, nb, width):
 
 
 _ORACLE_CACHE = {}
+_FIELD_CACHE = {}
+
+
+def _fields_cached(name):
+    if name not in _FIELD_CACHE:
+        _FIELD_CACHE[name] = fieldgen.workload_fields(name)
+    return _FIELD_CACHE[name]
 
 
 def _sampled_oracle(delta, order, nb, width, shells, tuples):
@@ -81,11 +88,11 @@ def _sample(plan_tuples, order, shells):
     return [tuple(int(v) for v in t) for t in plan_tuples if set(int(v) for v in t) <= allowed]
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-4)])
 def test_bispec_256_lognormal(gpu, precision, tol):
     w = fieldgen.WORKLOADS["bispec_256_lognormal"]
     say("generating the 256^3 lognormal field")
-    fields = fieldgen.workload_fields("bispec_256_lognormal")
+    fields = _fields_cached("bispec_256_lognormal")
     plan, B, bins, quot = _gpu_run(fields, 3, w["n_shells"], w["width"], precision)
     assert _integral(quot)
     _pair_sum_check(plan.tuples, plan.counts, w["N"], w["n_shells"], w["width"])
@@ -105,7 +112,7 @@ def test_bispec_256_lognormal(gpu, precision, tol):
 def test_trispec_256_lognormal(gpu, precision, tol):
     w = fieldgen.WORKLOADS["trispec_256_lognormal"]
     say("generating the 256^3 lognormal field")
-    fields = fieldgen.workload_fields("trispec_256_lognormal")
+    fields = _fields_cached("trispec_256_lognormal")
     plan, B, bins, quot = _gpu_run(fields, 4, w["n_shells"], w["width"], precision)
     assert _integral(quot)
     shells = [1, 2, 3, 12, 23, 24]
@@ -147,12 +154,13 @@ def test_bispec_grad_128x8(gpu):
     plan.close()
 
 
-def test_bispec_512_counts_and_sample(gpu):
+@pytest.mark.parametrize("precision", [1, 2])
+def test_bispec_512_counts_and_sample(gpu, precision):
     """The benchmark's plan: every count by the pair-sum rule, a tuple sample by the oracle."""
     w = fieldgen.WORKLOADS["bispec_512_lognormal"]
     say("generating the 512^3 lognormal field")
-    fields = fieldgen.workload_fields("bispec_512_lognormal")
-    plan, B, bins, quot = _gpu_run(fields, 3, w["n_shells"], w["width"], 1)
+    fields = _fields_cached("bispec_512_lognormal")
+    plan, B, bins, quot = _gpu_run(fields, 3, w["n_shells"], w["width"], precision)
     assert _integral(quot)
     _pair_sum_check(plan.tuples, plan.counts, w["N"], w["n_shells"], w["width"])
     shells = [1, 32, 64]

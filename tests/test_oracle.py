@@ -288,3 +288,18 @@ def test_exact_counts_match_fft_counts(order, nb, width):
     t = O.candidate_tuples(order, nb, O.is_alias_free(N, order, nb, width))
     assert np.array_equal(O.polygon_counts_exact(N, order, nb, width, t),
                           O.polygon_counts(N, order, nb, width, t))
+
+
+def test_physical_units_match_standard_estimators():
+    """With box side L: P(k) = V <|delta_k|^2> and B = V^2 <delta_k1 delta_k2 delta_k3>, delta_k = delta_hat / N^3."""
+    N, L = 16, 250.0
+    V = L ** 3
+    delta = fieldgen.gaussian_field(N, 21)
+    r2 = O.polyspectrum(delta, 2, 5, 1.0, box_length=L)
+    dk = np.fft.fftn(delta) / N ** 3
+    sid = O.shell_id_grid(N, 5, 1.0, half=False)
+    ref = np.array([V * np.mean(np.abs(dk[sid == s]) ** 2) for s in range(1, 6)])
+    np.testing.assert_allclose(r2["B"], ref, rtol=1e-11)
+    r3 = O.polyspectrum(delta, 3, 4, 1.0, box_length=L)
+    cnt, sums = O.bruteforce_polyspectrum(delta, 3, 4, 1.0, r3["tuples"])
+    np.testing.assert_allclose(r3["B"], V ** 2 * (sums.real / cnt) / float(N) ** 9, rtol=1e-10)
