@@ -209,8 +209,10 @@ def main():
     # algorithmic flops per launch: 2 per (closing triplet x point) + 1 per (pair x point)
     # for the contraction; 2 per (adjoint weight x point) + 1 per (pair x point) for the
     # adjoint product, whatever the tiles the kernels actually issue
-    ctr_roof = roofline("contract_tiles", ctr_ms, (2.0 * plan.n_closing + n_pairs) * G * batch, peak,
-                        load_traffic("contract_tiles", args.workload, args.precision))
+    # the FP16 split of an order-3 plan runs the shell-block aligned kernel
+    ctr_kernel = "contract_j3" if args.precision == "fp16" else "contract_tiles"
+    ctr_roof = roofline(ctr_kernel, ctr_ms, (2.0 * plan.n_closing + n_pairs) * G * batch, peak,
+                        load_traffic(ctr_kernel, args.workload, args.precision))
     n_w = adjoint_weight_entries(plan.tuples)
     adj_roof = roofline("adjoint_gemm", adj_ms, (2.0 * n_w + n_pairs) * G * batch, peak,
                         load_traffic("adjoint_gemm", args.workload, args.precision))
