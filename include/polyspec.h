@@ -171,6 +171,14 @@ polyspec_status polyspec_profile(polyspec_plan_t plan, int32_t enable);
  * int64 [POLYSPEC_N_PHASES], may be NULL) since the last read, and resets them. */
 polyspec_status polyspec_profile_read(polyspec_plan_t plan, double* h_ms, int64_t* h_launches);
 
+/* Matrix-core flops that one call issues in a phase, for the plan's current
+ * precision: every launched tile counts in full, including entries no tuple
+ * needs, so this is the work the hardware does rather than the algorithmic
+ * 2 flops per tuple and grid point.  Phases POLYSPEC_PH_CONTRACT and
+ * POLYSPEC_PH_ADJ_GEMM (order 3) have matrix-core work; every other phase gives 0.
+ * Host-only; no device work. */
+polyspec_status polyspec_issued_flops(polyspec_plan_t plan, int32_t phase, double* flops);
+
 /* Releases the plan and everything it allocated (not caller workspace).  Waits for
  * the plan's stream.  NULL is accepted. */
 polyspec_status polyspec_destroy(polyspec_plan_t plan);

@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "polyspec_destroy": (ctypes.c_int, [P]),
         "polyspec_profile": (ctypes.c_int, [P, ctypes.c_int32]),
         "polyspec_profile_read": (ctypes.c_int, [P, V, V]),
+        "polyspec_issued_flops": (ctypes.c_int, [P, ctypes.c_int32, D(ctypes.c_double)]),
         "polyspec_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "polyspec_last_error": (ctypes.c_char_p, [P]),
     }
@@ -192,6 +193,14 @@ def polyspec_profile_read(plan):
                                                 calls.ctypes.data_as(ctypes.c_void_p)),
            "polyspec_profile_read", plan)
     return {name: (float(ms[i]), int(calls[i])) for i, name in enumerate(PHASES)}
+
+
+def polyspec_issued_flops(plan, phase: str) -> float:
+    """Matrix-core flops one call issues in `phase` ("contract" or "adj_gemm")."""
+    out = ctypes.c_double(0.0)
+    _check(load_library().polyspec_issued_flops(plan, PHASES.index(phase), ctypes.byref(out)),
+           "polyspec_issued_flops", plan)
+    return out.value
 
 
 def polyspec_destroy(plan):

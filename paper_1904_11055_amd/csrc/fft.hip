@@ -30,11 +30,13 @@ struct FftCfg;
 template <>
 struct FftCfg<float> {
   static constexpr int kElems = 4096;
+  static constexpr int kColElems = 8192;   // P2: 16 pencils at N = 512, so runs of 128 bytes
   static constexpr int kRowElems = 2048;
 };
 template <>
 struct FftCfg<double> {
   static constexpr int kElems = 2048;
+  static constexpr int kColElems = 2048;
   static constexpr int kRowElems = 2048;
 };
 
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
                                                       const int* __restrict__ qmax,
                                                       cplx<T>* __restrict__ H2,
                                                       const cplx<T>* __restrict__ tw, Geom g) {
-  constexpr int P = FftCfg<T>::kElems / N;
+  constexpr int P = FftCfg<T>::kColElems / N;
   constexpr int NS = pencil_stride<N>();
   __shared__ cplx<T> buf[P * NS];
   __shared__ cplx<T> stw[stage_tw_size<N>()];
@@ -645,7 +647,7 @@ hipError_t launch_c2r_p1(const cplx<float>* box, const int16_t* sq, const int* q
 template <typename T>
 hipError_t launch_c2r_p2(const cplx<T>* H1, const int* qmax, cplx<T>* H2, const cplx<T>* tw, Geom g, int nz,
                          hipStream_t st) {
-  const int P = FftCfg<T>::kElems / g.N;
+  const int P = FftCfg<T>::kColElems / g.N;
   dim3 grid((g.B2 + P - 1) / P, g.N, nz);
   switch (g.N) {
 #define CASE(n) case n: hipLaunchKernelGGL((c2r_p2<T, n>), grid, dim3(kFftThreads), 0, st, H1, qmax, H2, tw, g); break;

@@ -93,6 +93,7 @@ struct polyspec_plan_s {
   int n_adj_active = 0;
   std::vector<int> pair_uv;
   // shell-block aligned order-3 schedule (FP16 split)
+  std::vector<int> wmask_host;     // adjoint: per v, bits 2 uc + mb of weight blocks
   bool jsched = false;
   int n_tiles_j = 0, ksteps_j = 0, n_chunks_j = 0;
 
@@ -752,6 +753,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
           if (lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] >= 0) wmask[v] |= 1 << (2 * (u / 16) + m / 32);
         }
     p->n_adj_active = p->nb;
+    p->wmask_host = wmask;
     PS_TRY(upload(p, &p->wmask_d, wmask));
   }
   return POLYSPEC_OK;
@@ -1035,6 +1037,28 @@ polyspec_status polyspec_profile_read(polyspec_plan_t p, double* h_ms, int64_t* 
     if (h_launches) h_launches[i] = p->prof_calls[i];
     p->prof_ms[i] = 0.0;
     p->prof_calls[i] = 0;
+  }
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_issued_flops(polyspec_plan_t p, int32_t phase, double* flops) {
+  if (!p || !flops) return POLYSPEC_ERR_INVALID_ARG;
+  if (phase < 0 || phase >= POLYSPEC_N_PHASES) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown phase");
+  const double terms = p->prec == POLYSPEC_FP32 ? 1.0 : 3.0;   // split: hi*hi + hi*lo + lo*hi
+  const double pts = (double)p->G * p->batch;
+  *flops = 0.0;
+  if (phase == POLYSPEC_PH_CONTRACT) {
+    // a 16 x 16 tile is 2 * 256 flops per grid point and product term
+    const bool aligned = p->jsched && p->prec == POLYSPEC_SPLIT_FP16 && p->ksteps_j % 4 == 0;
+    *flops = (aligned ? p->n_tiles_j : p->n_tiles) * 512.0 * terms * pts;
+  } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 3) {
+    // per partner shell v: the 32-row blocks of m with a weight, each times the
+    // 16-shell chunks of u <= v, as 32 x 32 x 16 products per 32 grid points
+    double blocks = 0.0;
+    for (int v = 0; v < p->nb; ++v)
+      for (int mb = 0; mb < 2; ++mb)
+        if (p->wmask_host[v] & (0x55 << mb)) blocks += v / 16 + 1;
+    *flops = blocks * 32.0 * 32.0 * 16.0 * 2.0 / 32.0 * terms * pts;
   }
   return POLYSPEC_OK;
 }

@@ -228,3 +228,18 @@ def test_precision_switch_after_shells(gpu):
         B = plan.contract().cpu().numpy()[0]
         assert _rel(B, ref["B"]) < tol, prec
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_issued_flops_cover_the_algorithmic_work(gpu, precision):
+    """Every launched tile counts, so the issued work is at least 2 flops per tuple and point."""
+    ps = _ps()
+    plan = ps.Plan(64, 3, 16, 1.0, precision=precision, device="cuda:0")
+    G = 64 ** 3
+    terms = 1 if precision == 0 else 3
+    ctr = ps.polyspec_issued_flops(plan.handle, "contract")
+    adj = ps.polyspec_issued_flops(plan.handle, "adj_gemm")
+    assert ctr >= 2.0 * plan.n_closing * G * terms
+    assert adj >= 2.0 * plan.n_closing * G * terms
+    assert ps.polyspec_issued_flops(plan.handle, "shell_p3") == 0.0
+    plan.close()
