@@ -22,6 +22,7 @@
 #include <utility>
 
 #include "common.h"
+#include "fft_core.h"
 #include "kernels.h"
 
 namespace ps {
@@ -773,12 +774,33 @@ constexpr int kAdjStageWords = kAdjVG * kAdjWPerV;
 constexpr int kAdjPiece = kAdjWPerV / kAdjThreads;          // words per thread per v step
 static_assert(kAdjPiece * kAdjThreads == kAdjWPerV, "a stage is copied in kAdjVG equal pieces");
 
-template <int PREC>
+// Fused epilogue (NF = N <= 512): the workgroup's 512 points are 512 / N whole rows
+// of x2, so the adjoint fields a_m of those rows are transformed to the half spectrum
+// q2 = 0..Kc right here (two rows m per complex FFT, the same real-to-complex pass as
+// the backward's first transform) and written to H2; the fields themselves never
+// reach HBM.  NF = 0 writes a_m to A for a separate transform (N = 1024).
+template <int NF>
+constexpr int adj_pencils() { return NF ? 32 * (kAdjPts / NF) : 0; }
+template <int NF>
+constexpr size_t adj_lds_bytes() {
+  const size_t stage = (size_t)2 * kAdjStageWords * sizeof(uint4);
+  if constexpr (NF == 0) {
+    return stage;
+  } else {
+    const size_t fft = ((size_t)adj_pencils<NF>() * pencil_stride<NF>() + stage_tw_size<NF>()) * sizeof(cplx<float>);
+    return fft > stage ? fft : stage;
+  }
+}
+
+template <int PREC, int NF>
 __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __restrict__ D,
                                                              const uint4* __restrict__ W,
                                                              const int* __restrict__ vmask, int n_shells,
-                                                             long long G, float* __restrict__ A) {
-  __shared__ uint4 wst[2][kAdjStageWords];
+                                                             long long G, float* __restrict__ A,
+                                                             cplx<float>* __restrict__ H2,
+                                                             const cplx<float>* __restrict__ tw, Geom g) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[adj_lds_bytes<NF>()];
+  auto wst = reinterpret_cast<uint4(*)[kAdjStageWords]>(lds);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -887,16 +909,55 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
   }
   // acc[pb][mb]: lane l, register i -> row m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4,
   // point l % 32 of column block pb
-  float* Ab = A + (size_t)b * n_shells * G + xw;
+  if constexpr (NF == 0) {
+    float* Ab = A + (size_t)b * n_shells * G + xw;
 #pragma unroll
-  for (int pb = 0; pb < kAdjPB; ++pb) {
+    for (int pb = 0; pb < kAdjPB; ++pb) {
 #pragma unroll
-    for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
-        if (m < n_shells) Ab[(size_t)m * G + 32 * pb] = acc[pb][mb][i];
+        for (int i = 0; i < 16; ++i) {
+          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+          if (m < n_shells) Ab[(size_t)m * G + 32 * pb] = acc[pb][mb][i];
+        }
       }
+    }
+  } else {
+    constexpr int P = adj_pencils<NF>();          // pencil rho * 32 + m / 2 holds rows m, m + 1 of x2-row rho
+    constexpr int NS = pencil_stride<NF>();
+    cplx<float>* buf = reinterpret_cast<cplx<float>*>(lds);
+    cplx<float>* stw = buf + P * NS;
+    __syncthreads();                              // every wave is done with the weight stages
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) {
+      const int x = wave * 32 * kAdjPB + 32 * pb + col;   // point within the workgroup
+      const int rho = x / NF, x2 = x % NF;
+#pragma unroll
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+          float* slot = reinterpret_cast<float*>(&buf[(rho * 32 + (m >> 1)) * NS + pad8(x2)]);
+          slot[m & 1] = acc[pb][mb][i];
+        }
+      }
+    }
+    build_stage_twiddles<float, NF, kAdjThreads>(stw, tw);
+    __syncthreads();
+    fft_block<float, NF, P, NS, -1, kAdjThreads>(buf, stw);
+    // half spectrum of each real row: A = (Z[c] + conj Z[-c]) / 2 (row m), B = (Z[c] - conj Z[-c]) / 2i (row m + 1)
+    const long long row0 = (long long)blockIdx.x * (kAdjPts / NF);
+    for (int u = threadIdx.x; u < 2 * P * g.B2; u += kAdjThreads) {
+      const int r = u / g.B2, c = u % g.B2;
+      const int pen = r >> 1;
+      const int m = 2 * (pen & 31) + (r & 1), rho = pen >> 5;
+      if (m >= n_shells) continue;
+      const cplx<float> Zp = buf[pen * NS + pad8(c)];
+      const cplx<float> Zm = buf[pen * NS + pad8((NF - c) & (NF - 1))];
+      cplx<float> v;
+      if ((r & 1) == 0) v = cplx<float>{0.5f * (Zp.re + Zm.re), 0.5f * (Zp.im - Zm.im)};
+      else v = cplx<float>{0.5f * (Zp.im + Zm.im), 0.5f * (Zm.re - Zp.re)};
+      H2[((size_t)(b * n_shells + m) * NF * NF + row0 + rho) * g.B2 + c] = v;
     }
   }
 }
@@ -981,12 +1042,27 @@ hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const
 }
 
 hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,
-                               float* A, int batch, hipStream_t st) {
+                               float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st) {
   dim3 grid((unsigned)(G / kAdjPts), batch);
-  if (prec == kFP32)
-    hipLaunchKernelGGL(adjoint_gemm<kFP32>, grid, dim3(kAdjThreads), 0, st, D, W, vmask, n_shells, G, A);
-  else
-    hipLaunchKernelGGL(adjoint_gemm<kBF16>, grid, dim3(kAdjThreads), 0, st, D, W, vmask, n_shells, G, A);
+  const bool fused = adjoint_fuses_rows(g.N);
+  if (fused == (H2 == nullptr) || fused == (A != nullptr)) return hipErrorInvalidValue;
+#define L(P, NF) hipLaunchKernelGGL((adjoint_gemm<P, NF>), grid, dim3(kAdjThreads), 0, st, D, W, vmask, n_shells, G, A, H2, tw, g)
+#define BY_N(P)                                  \
+  switch (g.N) {                                 \
+    case 32: L(P, 32); break;                    \
+    case 64: L(P, 64); break;                    \
+    case 128: L(P, 128); break;                  \
+    case 256: L(P, 256); break;                  \
+    case 512: L(P, 512); break;                  \
+    default: L(P, 0); break;                     \
+  }
+  if (prec == kFP32) {
+    BY_N(kFP32)
+  } else {
+    BY_N(kBF16)
+  }
+#undef BY_N
+#undef L
   return hipGetLastError();
 }
 

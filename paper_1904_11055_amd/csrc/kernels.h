@@ -100,8 +100,11 @@ hipError_t launch_reduce_dd(const double2* part, double2* tmp, int n_chunks, int
                             hipStream_t st);
 hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
                                   int n_closing, int prec, uint4* W, int batch, hipStream_t st);
+// N <= 512: the adjoint kernel also runs the first (x2 -> q2) transform of its fields
+// and writes H2 (A must be null); otherwise it writes the fields to A (H2 null).
+inline bool adjoint_fuses_rows(int N) { return N <= 512; }
 hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,
-                               float* A, int batch, hipStream_t st);
+                               float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
 
 // util.hip
 hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_t st);

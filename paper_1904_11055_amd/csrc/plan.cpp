@@ -255,7 +255,7 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
   L.H2 = align256(zf * p->N * p->N * p->B2 * sizeof(cplx<float>));
   L.D = align256(zf * (size_t)p->G * sizeof(float));
-  L.A = (p->order == 3) ? L.D : 0;
+  L.A = (p->order == 3 && !ps::adjoint_fuses_rows(p->N)) ? L.D : 0;   // adjoint fields only when not fused
   const size_t tiles = (size_t)std::max(p->n_tiles, p->n_tiles_j);
   L.partials = align256((size_t)p->batch * p->n_chunks * tiles * 256 * sizeof(float));
   L.red = align256((size_t)p->batch * p->red_groups * tiles * 256 * sizeof(double));
@@ -970,14 +970,15 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
   PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
            ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb, ncl,
                                       aprec, (uint4*)p->W, p->batch, st));
-  PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
-           ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G, p->A,
-                                   p->batch, st));
-  const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
-  PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
   Geom gs = make_geom(p, p->nb, 1);
   const cplx<float>* tw = (const cplx<float>*)p->tw32.p;
-  PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
+  const bool fused = ps::adjoint_fuses_rows(p->N);   // the kernel also runs the x2 -> q2 pass
+  PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
+           ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G,
+                                   fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gs, p->batch, st));
+  const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
+  PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
+  if (!fused) PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
   PS_TIMED(p, POLYSPEC_PH_ADJ_Q2, ps::launch_r2c_q2(p->H2, p->H1, tw, gs, nz, st));
   PS_TIMED(p, POLYSPEC_PH_ADJ_Q1, ps::launch_r2c_q1<true>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
                                     nz, st));
