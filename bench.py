@@ -64,11 +64,12 @@ def load_traffic(kernel: str, workload: str, precision: str):
 
 
 def adjoint_weight_entries(tuples) -> int:
-    """Distinct (m, (u <= v)) weights of the order-3 adjoint: each sorted closing
-    triplet (i, j, k) feeds a_k from d_i d_j, a_j from d_i d_k and a_i from d_j d_k."""
+    """Distinct adjoint weights (m, sorted rest of t without one position of m): each
+    closing tuple t feeds a_m for every position of m with the product of the others."""
     seen = set()
-    for i, j, k in tuples.tolist():
-        seen.update(((k, i, j), (j, i, k), (i, j, k)))
+    for t in tuples.tolist():
+        for p in range(len(t)):
+            seen.add((t[p],) + tuple(sorted(t[:p] + t[p + 1:])))
     return len(seen)
 
 
@@ -160,8 +161,9 @@ def main():
     import paper_1904_11055_amd as ps
 
     w = fieldgen.WORKLOADS[args.workload]
-    if w["order"] != 3:
-        raise SystemExit("the benchmark step needs an order-3 workload (forward + adjoint)")
+    order = w["order"]
+    if order not in (3, 4):
+        raise SystemExit("the benchmark step needs an order-3 or order-4 workload (forward + adjoint)")
     N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
     prec = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}[args.precision]
     dev = torch.device("cuda:0")
@@ -171,10 +173,10 @@ def main():
     torch.cuda.synchronize()
     log("building plan (float64 polygon counts)")
     t0 = time.perf_counter()
-    plan = ps.Plan(N, 3, nb, width, batch=batch, precision=prec, device=dev)
+    plan = ps.Plan(N, order, nb, width, batch=batch, precision=prec, device=dev)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
-    log(f"plan built in {plan_s:.2f} s: {plan.n_closing} closing triplets")
+    log(f"plan built in {plan_s:.2f} s: {plan.n_closing} closing tuples")
     G = N ** 3
 
     def step():
@@ -209,29 +211,34 @@ def main():
     ctr_ms = avg("contract")
     adj_ms = avg("adj_gemm")
     n_pairs = nb * (nb + 1) // 2
+    n_rests = n_pairs if order == 3 else nb * (nb + 1) * (nb + 2) // 6   # products the adjoint forms
     peak = PEAK_TFLOPS[args.precision]
     # algorithmic flops per launch: 2 per (closing triplet x point) + 1 per (pair x point)
     # for the contraction; 2 per (adjoint weight x point) + 1 per (pair x point) for the
     # adjoint product, whatever the tiles the kernels actually issue
     # the FP16 split of an order-3 plan runs the shell-block aligned kernel
-    ctr_kernel = "contract_j3" if args.precision == "fp16" else "contract_tiles"
+    ctr_kernel = "contract_j3" if (args.precision == "fp16" and order == 3) else "contract_tiles"
+    # algorithmic flops: order 3, 2 per (triplet x point) + 1 per (pair x point); order 4,
+    # 2 per (quadruple x point) + 1 per (pair x point) for the two pair products
     ctr_roof = roofline(ctr_kernel, ctr_ms, (2.0 * plan.n_closing + n_pairs) * G * batch,
                         ps.polyspec_issued_flops(plan.handle, "contract"), peak,
                         load_traffic(ctr_kernel, args.workload, args.precision))
     n_w = adjoint_weight_entries(plan.tuples)
-    adj_roof = roofline("adjoint_gemm", adj_ms, (2.0 * n_w + n_pairs) * G * batch,
+    adj_roof = roofline("adjoint_gemm" if order == 3 else "adjoint4_gemm", adj_ms,
+                        (2.0 * n_w + n_rests * (order - 2)) * G * batch,
                         ps.polyspec_issued_flops(plan.handle, "adj_gemm"), peak,
                         load_traffic("adjoint_gemm", args.workload, args.precision))
     dominant, other = (adj_roof, ctr_roof) if adj_ms >= ctr_ms else (ctr_roof, adj_roof)
     out = {
-        "metric": "bispectrum bin-triplets*gridpts/s at 512^3 (split-MFMA vs FP32); fwd+bwd ms",
+        "metric": ("bispectrum bin-triplets*gridpts/s at 512^3 (split-MFMA vs FP32); fwd+bwd ms" if order == 3
+                   else "trispectrum bin-quadruples*gridpts/s (split-MFMA); fwd+bwd ms"),
         "value": plan.n_closing * G * batch / (ms_step * 1e-3),
-        "unit": "bin-triplets*gridpts/s",
+        "unit": "bin-triplets*gridpts/s" if order == 3 else "bin-quadruples*gridpts/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": args.workload, "N": N, "order": 3, "n_shells": nb, "shell_width": width,
+        "config": {"workload": args.workload, "N": N, "order": order, "n_shells": nb, "shell_width": width,
                    "batch": batch, "field": w["field"], "seeds": w["seeds"], "n_closing": plan.n_closing,
                    "precision": args.precision, "parallelism": "none (1 GPU)"},
         "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "plan_s": plan_s,
@@ -258,7 +265,7 @@ def main():
     plan.close()
     del x
     torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and order == 3:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(fields[0], w, plan.n_closing * batch, args.cpu_planes)
     print(json.dumps(out), flush=True)

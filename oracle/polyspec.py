@@ -423,21 +423,27 @@ def polyspectrum(delta: np.ndarray, order: int, n_shells: int, width: float,
 # same operator: dL/d delta = C2R( sum_m M_m R2C(a_m) ), a_m = dL/d d_m.
 # ----------------------------------------------------------------------------
 def adjoint_weights(tuples: np.ndarray, weights: np.ndarray, n_shells: int) -> np.ndarray:
-    """W[m, pair] for order 3: every position p of t adds w_t to W[t_p, t without p]."""
-    pairs = pair_list(n_shells)
-    pidx = {(int(i), int(j)): n for n, (i, j) in enumerate(pairs)}
-    W = np.zeros((n_shells, len(pairs)))
-    for t, w in zip(np.asarray(tuples), np.asarray(weights, dtype=np.float64)):
-        for p in range(3):
+    """W[m, rest] for order n: every position p of t adds w_t to W[t_p, t without p].
+
+    `rest` runs over the sorted (n-1)-tuples (pairs for n = 3, triples for n = 4), so
+    dS_t / d d_m = sum of the products of the other n - 1 fields over the positions of m.
+    """
+    tuples = np.asarray(tuples)
+    order = tuples.shape[1]
+    rests = sorted_tuples(order - 1, n_shells)
+    ridx = {tuple(int(v) for v in r): n for n, r in enumerate(rests)}
+    W = np.zeros((n_shells, len(rests)))
+    for t, w in zip(tuples, np.asarray(weights, dtype=np.float64)):
+        for p in range(order):
             rest = tuple(sorted(int(v) for q, v in enumerate(t) if q != p))
-            W[int(t[p]) - 1, pidx[rest]] += w
+            W[int(t[p]) - 1, ridx[rest]] += w
     return W
 
 
 def gradient(delta: np.ndarray, order: int, n_shells: int, width: float, grad_B: np.ndarray,
              result: dict | None = None, box_length: float = 0.0,
              allow_aliasing: bool = False, chunk: int = 8192) -> np.ndarray:
-    """dL/d delta[x] for L with dL/dB_t = grad_B[t] over the closing tuples (orders 2, 3)."""
+    """dL/d delta[x] for L with dL/dB_t = grad_B[t] over the closing tuples (orders 2, 3, 4)."""
     delta = np.asarray(delta, dtype=np.float64)
     N = delta.shape[0]
     if result is None or "fields" not in result:
@@ -454,15 +460,18 @@ def gradient(delta: np.ndarray, order: int, n_shells: int, width: float, grad_B:
             i, j = int(t[0]) - 1, int(t[1]) - 1
             a[i] += wt * flat[j]
             a[j] += wt * flat[i]
-    elif order == 3:
+    elif order in (3, 4):
+        # a_m = sum over rests r of W[m, r] prod_{s in r} d_s
         W = adjoint_weights(tuples, w, n_shells)
-        pairs = pair_list(n_shells)
-        pi, pj = pairs[:, 0] - 1, pairs[:, 1] - 1
+        rests = sorted_tuples(order - 1, n_shells) - 1
         for x0 in range(0, flat.shape[1], chunk):
             blk = flat[:, x0:x0 + chunk]
-            a[:, x0:x0 + chunk] = W @ (blk[pi] * blk[pj])
+            prod = blk[rests[:, 0]].copy()
+            for c in range(1, order - 1):
+                prod *= blk[rests[:, c]]
+            a[:, x0:x0 + chunk] = W @ prod
     else:
-        raise ValueError("gradient supports orders 2 and 3")
+        raise ValueError("gradient supports orders 2, 3 and 4")
     sid = shell_id_grid(N, n_shells, width)
     g_hat = np.zeros((N, N, N // 2 + 1), dtype=np.complex128)
     for m in range(n_shells):

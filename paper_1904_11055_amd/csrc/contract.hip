@@ -792,6 +792,66 @@ constexpr size_t adj_lds_bytes() {
   }
 }
 
+// Writes the accumulated adjoint fields: acc[pb][mb] of lane l, register i is row
+// m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4 at point l % 32 of column block pb.
+template <int NF>
+__device__ __forceinline__ void adjoint_epilogue(const f32x16 (&acc)[kAdjPB][kAdjMaxMb], unsigned char* lds, int lane,
+                                                 int wave, int hh, int col, int b, long long xw, int n_shells,
+                                                 long long G, float* __restrict__ A, cplx<float>* __restrict__ H2,
+                                                 const cplx<float>* __restrict__ tw, const Geom& g) {
+  if constexpr (NF == 0) {
+    float* Ab = A + (size_t)b * n_shells * G + xw;
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) {
+#pragma unroll
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+          if (m < n_shells) Ab[(size_t)m * G + 32 * pb] = acc[pb][mb][i];
+        }
+      }
+    }
+  } else {
+    constexpr int P = adj_pencils<NF>();          // pencil rho * 32 + m / 2 holds rows m, m + 1 of x2-row rho
+    constexpr int NS = pencil_stride<NF>();
+    cplx<float>* buf = reinterpret_cast<cplx<float>*>(lds);
+    cplx<float>* stw = buf + P * NS;
+    __syncthreads();                              // every wave is done with the weight stages
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) {
+      const int x = wave * 32 * kAdjPB + 32 * pb + col;   // point within the workgroup
+      const int rho = x / NF, x2 = x % NF;
+#pragma unroll
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+          float* slot = reinterpret_cast<float*>(&buf[(rho * 32 + (m >> 1)) * NS + pad8(x2)]);
+          slot[m & 1] = acc[pb][mb][i];
+        }
+      }
+    }
+    build_stage_twiddles<float, NF, kAdjThreads>(stw, tw);
+    __syncthreads();
+    fft_block<float, NF, P, NS, -1, kAdjThreads>(buf, stw);
+    // half spectrum of each real row: A = (Z[c] + conj Z[-c]) / 2 (row m), B = (Z[c] - conj Z[-c]) / 2i (row m + 1)
+    const long long row0 = (long long)blockIdx.x * (kAdjPts / NF);
+    for (int u = threadIdx.x; u < 2 * P * g.B2; u += kAdjThreads) {
+      const int r = u / g.B2, c = u % g.B2;
+      const int pen = r >> 1;
+      const int m = 2 * (pen & 31) + (r & 1), rho = pen >> 5;
+      if (m >= n_shells) continue;
+      const cplx<float> Zp = buf[pen * NS + pad8(c)];
+      const cplx<float> Zm = buf[pen * NS + pad8((NF - c) & (NF - 1))];
+      cplx<float> v;
+      if ((r & 1) == 0) v = cplx<float>{0.5f * (Zp.re + Zm.re), 0.5f * (Zp.im - Zm.im)};
+      else v = cplx<float>{0.5f * (Zp.im + Zm.im), 0.5f * (Zm.re - Zp.re)};
+      H2[((size_t)(b * n_shells + m) * NF * NF + row0 + rho) * g.B2 + c] = v;
+    }
+  }
+}
+
 template <int PREC, int NF>
 __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __restrict__ D,
                                                              const uint4* __restrict__ W,
@@ -907,59 +967,167 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
       }
     }
   }
-  // acc[pb][mb]: lane l, register i -> row m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4,
-  // point l % 32 of column block pb
-  if constexpr (NF == 0) {
-    float* Ab = A + (size_t)b * n_shells * G + xw;
+  adjoint_epilogue<NF>(acc, lds, lane, wave, hh, col, b, xw, n_shells, G, A, H2, tw, g);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint, order 4 (at most 32 shells).  With the closing 4-tuples t and their
+// weights w_t = dL/dB_t f / (N^3 n_t),
+//   a_m[x] = sum over sorted (u <= v <= w) of W4[m][(u, v, w)] d_u d_v d_w,
+// W4[m][(u, v, w)] = (times m occurs in t) w_t for t = sort(m, u, v, w).  Grouped by
+// the largest shell w and then v, the kernel forms Y_(v,w) = W4_(v,w) D_w on the
+// matrix cores, D_w the fields d_u d_w of the lane's points, and adds d_v Y_(v,w).
+// ---------------------------------------------------------------------------
+// W4 in operand order: item it = w (w + 1) / 2 + v, 16-shell chunk uc of u, lane l holds
+// row m = l % 32 and u = 16 uc + 8 (l / 32) + r (r = 0..7; zero when u > v), as two
+// 16-byte words (hi / lo bf16, or values 0..3 / 4..7 in float32).
+__global__ void adjoint4_weights(const double* __restrict__ grad, const double* __restrict__ fnorm,
+                                 const int* __restrict__ lookup /*[nb^4] closing index or -1*/, int n_shells,
+                                 int n_closing, int prec, uint4* __restrict__ W) {
+  const int m = threadIdx.x;            // 0..31
+  const int u = blockIdx.x;             // 0..31
+  const int it = blockIdx.y;            // item (w, v)
+  const int b = blockIdx.z;
+  int w = 0;
+  while ((w + 1) * (w + 2) / 2 <= it) ++w;
+  const int v = it - w * (w + 1) / 2;
+  float val = 0.f;
+  if (m < n_shells && u < n_shells && u <= v) {
+    int t[4] = {m, u, v, w};
 #pragma unroll
-    for (int pb = 0; pb < kAdjPB; ++pb) {
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
-          if (m < n_shells) Ab[(size_t)m * G + 32 * pb] = acc[pb][mb][i];
-        }
-      }
-    }
-  } else {
-    constexpr int P = adj_pencils<NF>();          // pencil rho * 32 + m / 2 holds rows m, m + 1 of x2-row rho
-    constexpr int NS = pencil_stride<NF>();
-    cplx<float>* buf = reinterpret_cast<cplx<float>*>(lds);
-    cplx<float>* stw = buf + P * NS;
-    __syncthreads();                              // every wave is done with the weight stages
-#pragma unroll
-    for (int pb = 0; pb < kAdjPB; ++pb) {
-      const int x = wave * 32 * kAdjPB + 32 * pb + col;   // point within the workgroup
-      const int rho = x / NF, x2 = x % NF;
-#pragma unroll
-      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
-          float* slot = reinterpret_cast<float*>(&buf[(rho * 32 + (m >> 1)) * NS + pad8(x2)]);
-          slot[m & 1] = acc[pb][mb][i];
-        }
-      }
-    }
-    build_stage_twiddles<float, NF, kAdjThreads>(stw, tw);
-    __syncthreads();
-    fft_block<float, NF, P, NS, -1, kAdjThreads>(buf, stw);
-    // half spectrum of each real row: A = (Z[c] + conj Z[-c]) / 2 (row m), B = (Z[c] - conj Z[-c]) / 2i (row m + 1)
-    const long long row0 = (long long)blockIdx.x * (kAdjPts / NF);
-    for (int u = threadIdx.x; u < 2 * P * g.B2; u += kAdjThreads) {
-      const int r = u / g.B2, c = u % g.B2;
-      const int pen = r >> 1;
-      const int m = 2 * (pen & 31) + (r & 1), rho = pen >> 5;
-      if (m >= n_shells) continue;
-      const cplx<float> Zp = buf[pen * NS + pad8(c)];
-      const cplx<float> Zm = buf[pen * NS + pad8((NF - c) & (NF - 1))];
-      cplx<float> v;
-      if ((r & 1) == 0) v = cplx<float>{0.5f * (Zp.re + Zm.re), 0.5f * (Zp.im - Zm.im)};
-      else v = cplx<float>{0.5f * (Zp.im + Zm.im), 0.5f * (Zm.re - Zp.re)};
-      H2[((size_t)(b * n_shells + m) * NF * NF + row0 + rho) * g.B2 + c] = v;
+      for (int c = 0; c < 3 - a; ++c)
+        if (t[c] > t[c + 1]) { const int x = t[c]; t[c] = t[c + 1]; t[c + 1] = x; }
+    const int id = lookup[(((size_t)t[0] * n_shells + t[1]) * n_shells + t[2]) * n_shells + t[3]];
+    if (id >= 0) {
+      const int mult = (t[0] == m) + (t[1] == m) + (t[2] == m) + (t[3] == m);
+      val = (float)((double)mult * grad[(size_t)b * n_closing + id] * fnorm[id]);
     }
   }
+  const int n_items = n_shells * (n_shells + 1) / 2;
+  const int uc = u >> 4, q = u & 15, hh = q >> 3, r = q & 7;
+  const int lane = 32 * hh + m;
+  uint4* base = W + (((size_t)b * n_items + it) * 2 + uc) * 2 * 64;
+  if (prec == kFP32) {
+    float* dst = reinterpret_cast<float*>(&base[(r < 4 ? 0 : 64) + lane]);
+    dst[r & 3] = val;
+  } else {
+    const unsigned bits = __float_as_uint(val);
+    const float h = __uint_as_float(bits & 0xffff0000u);
+    reinterpret_cast<unsigned short*>(&base[lane])[r] = (unsigned short)(bits >> 16);
+    reinterpret_cast<unsigned short*>(&base[64 + lane])[r] = __builtin_bit_cast(unsigned short, (__bf16)(val - h));
+  }
+}
+
+template <int NF>
+constexpr size_t adj4_lds_bytes() {
+  const size_t stage = (size_t)kAdj4MaxShells * kAdj4WordsPerItem * sizeof(uint4);   // the items of one w
+  if constexpr (NF == 0) {
+    return stage;
+  } else {
+    const size_t fft = ((size_t)adj_pencils<NF>() * pencil_stride<NF>() + stage_tw_size<NF>()) * sizeof(cplx<float>);
+    return fft > stage ? fft : stage;
+  }
+}
+
+// A workgroup of 8 waves owns 512 grid points (64 per wave, two column blocks) and
+// all shells m < 32.  For each w the weights of the items (w, v <= w) are staged in
+// LDS and the fields of the lane's points, scaled by d_w, become the B operands.
+template <int PREC, int NF>
+__global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __restrict__ D,
+                                                              const uint4* __restrict__ W,
+                                                              const int* __restrict__ imask, int n_shells,
+                                                              long long G, float* __restrict__ A,
+                                                              cplx<float>* __restrict__ H2,
+                                                              const cplx<float>* __restrict__ tw, Geom g) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[adj4_lds_bytes<NF>()];
+  uint4* wst = reinterpret_cast<uint4*>(lds);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hh = lane >> 5, col = lane & 31;
+  const int b = blockIdx.y;
+  const long long xw = (long long)blockIdx.x * kAdjPts + wave * 32 * kAdjPB + col;
+  const float* Db = D + (size_t)b * n_shells * G;
+  const int n_items = n_shells * (n_shells + 1) / 2;
+  const uint4* Wb = W + (size_t)b * n_items * kAdj4WordsPerItem;
+
+  // fields at the lane's points: F[pb][uc][r] = d_u, u = 16 uc + 8 hh + r
+  float F[kAdjPB][2][8];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+    for (int uc = 0; uc < 2; ++uc)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int sh = 16 * uc + 8 * hh + r;
+        F[pb][uc][r] = sh < n_shells ? Db[(size_t)sh * G + xw + 32 * pb] : 0.f;
+      }
+  f32x16 acc[kAdjPB][kAdjMaxMb];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+    for (int mb = 0; mb < kAdjMaxMb; ++mb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[pb][mb][i] = 0.f;
+
+  for (int w = 0; w < n_shells; ++w) {
+    const int it0 = w * (w + 1) / 2;
+    __syncthreads();                              // the previous w's stage is consumed
+    for (int i = tid; i < (w + 1) * kAdj4WordsPerItem; i += kAdjThreads) wst[i] = Wb[(size_t)it0 * kAdj4WordsPerItem + i];
+    float dw[kAdjPB];
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) dw[pb] = Db[(size_t)w * G + xw + 32 * pb];
+    Operand<PREC> Bu[kAdjPB][2];
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+      for (int uc = 0; uc < 2; ++uc) {
+        float x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = F[pb][uc][r] * dw[pb];
+        Bu[pb][uc] = make_operand<PREC>(x, 1.f);
+      }
+    const int my_mask = lane <= w ? imask[it0 + lane] : 0;   // items (w, v = lane)
+    __syncthreads();
+#pragma unroll
+    for (int vc = 0; vc < 2; ++vc) {
+#pragma unroll
+      for (int vv = 0; vv < 16; ++vv) {
+        const int v = 16 * vc + vv;
+        if (v > w) break;
+        const int mask = __builtin_amdgcn_readlane(my_mask, v);   // bit uc
+        if (!mask) continue;
+        const uint4* wv = wst + v * kAdj4WordsPerItem;
+        float dv[kAdjPB];
+#pragma unroll
+        for (int pb = 0; pb < kAdjPB; ++pb) {
+          const unsigned own = __float_as_uint(F[pb][vc][vv % 8]);
+          const auto sw = __builtin_amdgcn_permlane32_swap(own, own, false, false);
+          dv[pb] = __uint_as_float(vv / 8 == 0 ? sw[0] : sw[1]);
+        }
+        Operand<PREC> Wop[2];
+#pragma unroll
+        for (int uc = 0; uc <= vc; ++uc) Wop[uc] = op_from_words<PREC>(wv[uc * 128 + lane], wv[uc * 128 + 64 + lane]);
+        f32x16 Y[kAdjPB];
+#pragma unroll
+        for (int uc = 0; uc <= vc; ++uc) {
+#pragma unroll
+          for (int pb = 0; pb < kAdjPB; ++pb) {
+            if (uc == 0) mma32_first<PREC>(Y[pb], Wop[uc], Bu[pb][uc]);
+            else mma32<PREC>(Y[pb], Wop[uc], Bu[pb][uc]);
+          }
+        }
+#pragma unroll
+        for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[pb][0][i] += dv[pb] * Y[pb][i];
+      }
+    }
+  }
+  __syncthreads();
+  adjoint_epilogue<NF>(acc, lds, lane, wave, hh, col, b, xw, n_shells, G, A, H2, tw, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,6 +1206,40 @@ hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const
                                   int n_closing, int prec, uint4* W, int batch, hipStream_t st) {
   dim3 grid(64, n_shells, batch);
   hipLaunchKernelGGL(adjoint_weights, grid, dim3(64), 0, st, grad, fnorm, lookup, n_shells, n_closing, prec, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint4_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
+                                   int n_closing, int prec, uint4* W, int batch, hipStream_t st) {
+  if (n_shells > kAdj4MaxShells) return hipErrorInvalidValue;
+  dim3 grid(32, n_shells * (n_shells + 1) / 2, batch);
+  hipLaunchKernelGGL(adjoint4_weights, grid, dim3(32), 0, st, grad, fnorm, lookup, n_shells, n_closing, prec, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint4_gemm(int prec, const float* D, const uint4* W, const int* imask, int n_shells, long long G,
+                                float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st) {
+  if (n_shells > kAdj4MaxShells) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(G / kAdjPts), batch);
+  const bool fused = adjoint_fuses_rows(g.N);
+  if (fused == (H2 == nullptr) || fused == (A != nullptr)) return hipErrorInvalidValue;
+#define L(P, NF) hipLaunchKernelGGL((adjoint4_gemm<P, NF>), grid, dim3(kAdjThreads), 0, st, D, W, imask, n_shells, G, A, H2, tw, g)
+#define BY_N(P)                                  \
+  switch (g.N) {                                 \
+    case 32: L(P, 32); break;                    \
+    case 64: L(P, 64); break;                    \
+    case 128: L(P, 128); break;                  \
+    case 256: L(P, 256); break;                  \
+    case 512: L(P, 512); break;                  \
+    default: L(P, 0); break;                     \
+  }
+  if (prec == kFP32) {
+    BY_N(kFP32)
+  } else {
+    BY_N(kBF16)
+  }
+#undef BY_N
+#undef L
   return hipGetLastError();
 }
 

@@ -105,6 +105,13 @@ hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const
 inline bool adjoint_fuses_rows(int N) { return N <= 512; }
 hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,
                                float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
+// Order 4 (n_shells <= kAdj4MaxShells): W4[b][item (w, v <= w)][uc][hi, lo][lane], item = w (w + 1) / 2 + v.
+constexpr int kAdj4MaxShells = 32;
+constexpr int kAdj4WordsPerItem = 2 * 2 * 64;
+hipError_t launch_adjoint4_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
+                                   int n_closing, int prec, uint4* W, int batch, hipStream_t st);
+hipError_t launch_adjoint4_gemm(int prec, const float* D, const uint4* W, const int* imask, int n_shells, long long G,
+                                float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
 
 // util.hip
 hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_t st);

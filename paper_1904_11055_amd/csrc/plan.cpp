@@ -251,16 +251,19 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   const size_t zf = (size_t)p->batch * p->nb;
   L.box = align256((size_t)p->batch * box_elems * sizeof(cplx<float>));
-  L.gbox = (p->order == 3) ? L.box : 0;
+  const bool adjoint = p->order == 3 || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
+  L.gbox = adjoint ? L.box : 0;
   L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
   L.H2 = align256(zf * p->N * p->N * p->B2 * sizeof(cplx<float>));
   L.D = align256(zf * (size_t)p->G * sizeof(float));
-  L.A = (p->order == 3 && !ps::adjoint_fuses_rows(p->N)) ? L.D : 0;   // adjoint fields only when not fused
+  L.A = (adjoint && !ps::adjoint_fuses_rows(p->N)) ? L.D : 0;   // adjoint fields only when not fused
   const size_t tiles = (size_t)std::max(p->n_tiles, p->n_tiles_j);
   L.partials = align256((size_t)p->batch * p->n_chunks * tiles * 256 * sizeof(float));
   L.red = align256((size_t)p->batch * p->red_groups * tiles * 256 * sizeof(double));
   L.absmax = align256(zf * sizeof(unsigned)) + align256(zf * ps::kAbsmaxSpreadHost * sizeof(unsigned));
-  L.W = (p->order == 3) ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16) : 0;
+  L.W = p->order == 3 ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16)
+        : adjoint ? align256((size_t)p->batch * (p->nb * (p->nb + 1) / 2) * ps::kAdj4WordsPerItem * 16)
+                  : 0;
   L.total = L.box + L.gbox + L.H1 + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
   return L;
 }
@@ -720,7 +723,9 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     phys = std::pow(V, p->order - 1) / std::pow((double)p->N, 3 * p->order);
   }
   std::vector<int> lookup;
-  if (p->order == 3) lookup.assign((size_t)p->nb * p->nb * p->nb, -1);
+  const bool adj3 = p->order == 3, adj4 = p->order == 4 && p->nb <= ps::kAdj4MaxShells;
+  if (adj3) lookup.assign((size_t)p->nb * p->nb * p->nb, -1);
+  if (adj4) lookup.assign((size_t)p->nb * p->nb * p->nb * p->nb, -1);
   for (size_t c = 0; c < nc; ++c) {
     if (p->cand_count[c] <= 0) continue;
     const int k = (int)p->closing.size();
@@ -730,9 +735,13 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     ent.push_back(ent_of_cand[c]);
     if (p->jsched) ent_j.push_back(ent_j_of_cand[c]);
     fnorm.push_back(phys / (N3 * (double)p->cand_count[c]));
-    if (p->order == 3) {
+    if (adj3) {
       const int* t = &p->cand[c * 3];
       lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] = k;
+    }
+    if (adj4) {
+      const int* t = &p->cand[c * 4];
+      lookup[(((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]) * p->nb + t[3]] = k;
     }
   }
   PS_TRY(upload(p, &p->ent_d, ent));
@@ -755,6 +764,24 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     p->n_adj_active = p->nb;
     p->wmask_host = wmask;
     PS_TRY(upload(p, &p->wmask_d, wmask));
+  }
+  if (adj4) {
+    PS_TRY(upload(p, &p->lookup_d, lookup));
+    // for each item (w, v <= w): which 16-shell chunks uc of u <= v hold a weight
+    // W4[m][(u, v, w)] (bit uc); the order-4 adjoint skips items without any
+    const int nb = p->nb;
+    std::vector<int> imask(nb * (nb + 1) / 2, 0);
+    for (int w = 0; w < nb; ++w)
+      for (int v = 0; v <= w; ++v)
+        for (int u = 0; u <= v; ++u)
+          for (int m = 0; m < nb; ++m) {
+            int t[4] = {m, u, v, w};
+            std::sort(t, t + 4);
+            if (lookup[(((size_t)t[0] * nb + t[1]) * nb + t[2]) * nb + t[3]] >= 0)
+              imask[w * (w + 1) / 2 + v] |= 1 << (u / 16);
+          }
+    p->wmask_host = imask;
+    PS_TRY(upload(p, &p->wmask_d, imask));
   }
   return POLYSPEC_OK;
 }
@@ -958,7 +985,8 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
 
 polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, float* d_grad_delta) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
-  if (p->order != 3) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward is implemented for order 3");
+  if (p->order != 3 && !(p->order == 4 && p->nb <= ps::kAdj4MaxShells))
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward is implemented for order 3, and order 4 with at most 32 shells");
   if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM)
     return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward needs real-space input");
   if (!d_grad_out || !d_grad_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null pointer");
@@ -967,15 +995,24 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
   const int nz = p->batch * p->nb;
   const int ncl = (int)p->closing.size();
   const int aprec = (p->prec == POLYSPEC_FP32) ? 0 : 1;  // FP16 mode uses the bf16 split here
-  PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
-           ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb, ncl,
-                                      aprec, (uint4*)p->W, p->batch, st));
   Geom gs = make_geom(p, p->nb, 1);
   const cplx<float>* tw = (const cplx<float>*)p->tw32.p;
   const bool fused = ps::adjoint_fuses_rows(p->N);   // the kernel also runs the x2 -> q2 pass
-  PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
-           ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G,
-                                   fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gs, p->batch, st));
+  if (p->order == 3) {
+    PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
+             ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb,
+                                        ncl, aprec, (uint4*)p->W, p->batch, st));
+    PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
+             ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G,
+                                     fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gs, p->batch, st));
+  } else {
+    PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
+             ps::launch_adjoint4_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb,
+                                         ncl, aprec, (uint4*)p->W, p->batch, st));
+    PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
+             ps::launch_adjoint4_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G,
+                                      fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gs, p->batch, st));
+  }
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
   if (!fused) PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
@@ -1052,6 +1089,13 @@ polyspec_status polyspec_issued_flops(polyspec_plan_t p, int32_t phase, double* 
     // a 16 x 16 tile is 2 * 256 flops per grid point and product term
     const bool aligned = p->jsched && p->prec == POLYSPEC_SPLIT_FP16 && p->ksteps_j % 4 == 0;
     *flops = (aligned ? p->n_tiles_j : p->n_tiles) * 512.0 * terms * pts;
+  } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 4 && p->nb <= ps::kAdj4MaxShells) {
+    // per item (w, v): the 16-shell chunks of u <= v, one 32-row block of m
+    double blocks = 0.0;
+    for (int w = 0; w < p->nb; ++w)
+      for (int v = 0; v <= w; ++v)
+        if (p->wmask_host[w * (w + 1) / 2 + v]) blocks += v / 16 + 1;
+    *flops = blocks * 32.0 * 32.0 * 16.0 * 2.0 / 32.0 * terms * pts;
   } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 3) {
     // per partner shell v: the 32-row blocks of m with a weight, each times the
     // 16-shell chunks of u <= v, as 32 x 32 x 16 products per 32 grid points

@@ -303,3 +303,38 @@ def test_physical_units_match_standard_estimators():
     r3 = O.polyspectrum(delta, 3, 4, 1.0, box_length=L)
     cnt, sums = O.bruteforce_polyspectrum(delta, 3, 4, 1.0, r3["tuples"])
     np.testing.assert_allclose(r3["B"], V ** 2 * (sums.real / cnt) / float(N) ** 9, rtol=1e-10)
+
+
+@pytest.mark.parametrize("width,allow", [(1.0, False), (1.0, True)])
+def test_gradient_trispectrum_central_differences(width, allow):
+    """Order 4 (incl. an aliased plan): the adjoint against central differences of the FP64 forward."""
+    N = 16
+    nb = 3 if not allow else 4
+    delta = fieldgen.lognormal_field(N, 41)
+    kw = dict(allow_aliasing=allow)
+    target = 0.5 * O.polyspectrum(fieldgen.lognormal_field(N, 42), 4, nb, width, **kw)["B"]
+    r = O.polyspectrum(delta, 4, nb, width, return_fields=True, **kw)
+    counts = r["candidate_counts"]
+    grad = O.gradient(delta, 4, nb, width, 2.0 * (r["B"] - target), result=r, allow_aliasing=allow)
+
+    def loss(dl):
+        return np.sum((O.polyspectrum(dl, 4, nb, width, counts=counts, **kw)["B"] - target) ** 2)
+
+    rng = np.random.default_rng(5)
+    eps = 1e-3
+    for flat in rng.choice(N ** 3, size=6, replace=False):
+        idx = np.unravel_index(flat, (N, N, N))
+        dp = delta.copy(); dp[idx] += eps
+        dm = delta.copy(); dm[idx] -= eps
+        fd = (loss(dp) - loss(dm)) / (2 * eps)
+        assert abs(fd - grad[idx]) <= 1e-6 * np.abs(grad).max()
+
+
+def test_adjoint_weights_sum_rule():
+    """sum over m and rests of W = (order) * sum_t w_t: each tuple spreads its weight over its positions."""
+    for order, nb in ((3, 6), (4, 5)):
+        t = O.candidate_tuples(order, nb, True)
+        w = np.linspace(0.5, 2.0, len(t))
+        W = O.adjoint_weights(t, w, nb)
+        assert np.isclose(W.sum(), order * w.sum())
+        assert W.shape == (nb, len(O.sorted_tuples(order - 1, nb)))
