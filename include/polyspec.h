@@ -107,7 +107,12 @@ polyspec_status polyspec_contract(polyspec_plan_t plan, double* d_out, double* d
 /* Adjoint of shells + contract (not in the paper): given dL/dB_t in d_grad_out
  * (float64 [batch][n_closing]), writes dL/d delta to d_grad_delta as float32
  * [batch][N][N][N], using the shell fields of the last polyspec_shells call.
- * Order 3 only (POLYSPEC_ERR_UNSUPPORTED otherwise); real-space input only. */
+ * Each position of a closing tuple contributes dL/dB_t f/(N^3 n_t) times the
+ * product of the other shell fields to a_m of its shell m; dL/d delta is the
+ * unnormalised C2R of sum_m [s(q) = m] R2C(a_m).  Orders 3 and 4 (order 4 with
+ * at most 32 shells); POLYSPEC_ERR_UNSUPPORTED otherwise.  Real-space input only.
+ * The adjoint product runs in float32 for POLYSPEC_FP32 and as the BF16 split
+ * otherwise. */
 polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out, float* d_grad_delta);
 
 /* Bytes of device workspace the plan needs for shells, contract and backward. */
