@@ -225,13 +225,14 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restr
   float* o = out + (size_t)z * G + (size_t)row0 * N;
   float amax = 0.f;
 #pragma unroll
-  for (int m = 0; m < 2 * E; ++m) {
-    const int u = threadIdx.x + m * kFftThreads;  // output index within the 2P rows
-    const int r = u / N, x2 = u % N;
-    const cplx<T> v = buf[(r >> 1) * NS + pad8(x2)];
-    const float val = (r & 1) ? v.im : v.re;
-    o[u] = val;
-    amax = fmaxf(amax, fabsf(val));
+  for (int m = 0; m < E; ++m) {
+    // one LDS read gives both rows of the pair: the real part is row 2 pp, the imaginary row 2 pp + 1
+    const int u = threadIdx.x + m * kFftThreads;
+    const int pp = u / N, x2 = u % N;
+    const cplx<T> v = buf[pp * NS + pad8(x2)];
+    o[(size_t)(2 * pp) * N + x2] = v.re;
+    o[(size_t)(2 * pp + 1) * N + x2] = v.im;
+    amax = fmaxf(amax, fmaxf(fabsf(v.re), fabsf(v.im)));
   }
   if (absmax != nullptr) {
     // block maximum, then one atomic into one of kAbsmaxSpread words of this field
