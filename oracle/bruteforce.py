@@ -9,6 +9,8 @@ explicitly; it is slow and meant for tiny grids (16^3, 32^3).
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 
 from .polyspec import shell_of_squared_norm
@@ -48,35 +50,28 @@ def bruteforce_polyspectrum(delta: np.ndarray, order: int, n_shells: int, width:
     counts = np.zeros(len(tuples), dtype=np.int64)
     sums = np.zeros(len(tuples), dtype=np.complex128)
     for n, t in enumerate(np.asarray(tuples)):
+        if len(t) != order or order < 2:
+            raise ValueError("tuples must have `order` entries, order >= 2")
         first = [vecs[int(s) - 1] for s in t[:-1]]
         last = int(t[-1])
-        if order == 2:
-            q_last = _wrap(-first[0], N)
-            ok = shell_of_squared_norm((q_last ** 2).sum(-1), n_shells, width) == last
-            counts[n] = ok.sum()
-            sums[n] = (value(first[0]) * value(q_last))[ok].sum()
-        elif order == 3:
-            a, b = first
-            tot = a[:, None, :] + b[None, :, :]
+        # the last two free vectors are enumerated as a grid, any earlier ones one
+        # combination at a time; q_n closes the polygon
+        head, (a, b) = first[:-2], ([np.zeros((1, 3), dtype=np.int64)] + first)[-2:]
+        cnt = 0
+        acc = 0j
+        for combo in itertools.product(*[range(len(h)) for h in head]):
+            base = np.zeros(3, dtype=np.int64)
+            w = 1.0 + 0j
+            for h, i in zip(head, combo):
+                base = base + h[i]
+                w *= value(h[i])
+            tot = base[None, None, :] + a[:, None, :] + b[None, :, :]
             q_last = _wrap(-tot, N)
             ok = shell_of_squared_norm((q_last ** 2).sum(-1), n_shells, width) == last
-            prod = value(a)[:, None] * value(b)[None, :] * value(q_last)
-            counts[n] = ok.sum()
-            sums[n] = prod[ok].sum()
-        elif order == 4:
-            a, b, c = first
-            va, vb, vc = value(a), value(b), value(c)
-            cnt = 0
-            acc = 0j
-            for ia in range(len(a)):
-                tot = a[ia][None, None, :] + b[:, None, :] + c[None, :, :]
-                q_last = _wrap(-tot, N)
-                ok = shell_of_squared_norm((q_last ** 2).sum(-1), n_shells, width) == last
-                prod = va[ia] * vb[:, None] * vc[None, :] * value(q_last)
-                cnt += int(ok.sum())
-                acc += prod[ok].sum()
-            counts[n] = cnt
-            sums[n] = acc
-        else:
-            raise ValueError("bruteforce supports orders 2, 3 and 4")
+            va = value(a) if order > 2 else np.ones(1)
+            prod = w * va[:, None] * value(b)[None, :] * value(q_last)
+            cnt += int(ok.sum())
+            acc += prod[ok].sum()
+        counts[n] = cnt
+        sums[n] = acc
     return counts, sums

@@ -70,7 +70,7 @@ __all__ = [
     "outer_radius", "is_alias_free", "sorted_tuples", "candidate_tuples", "pair_list",
     "shell_mode_counts", "shell_fields", "shell_fields_from_hat", "count_fields",
     "shell_fields_on_planes", "product_sums", "tuple_product_sums", "counts_from_sums", "polygon_counts",
-    "pair_counts", "polygon_counts_exact",
+    "pair_counts", "triple_counts", "polygon_counts_exact", "triple_list",
     "polyspectrum", "adjoint_weights", "gradient", "physical_factor",
 ]
 
@@ -225,41 +225,48 @@ def shell_fields_on_planes(delta_hat: np.ndarray, N: int, n_shells: int, width: 
 # Product sums (Sec. 2: the grid sum of products of the shell fields;
 # Appendix A: sum over [x] of prod_j FFTW(I~_{k_j})).
 # ----------------------------------------------------------------------------
-def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192, compensated: bool = False):
-    """S_t = sum_x prod_j fields[t_j - 1][x] in FP64, for orders 2, 3 and 4.
+def triple_list(n_shells: int) -> np.ndarray:
+    """Triples (i, j, k), 1 <= i <= j <= k <= N_b, lexicographic."""
+    return sorted_tuples(3, n_shells)
 
-    The grid is summed in chunks; pair products d_i d_j are formed once per chunk
-    and multiplied against the remaining factor(s) with a matrix product.  With
-    compensated=True the chunk results are added with error-free transformations
-    and the pair (hi, lo) with S = hi + lo is returned (used for polygon counts,
-    which reach 10^12 and must round to the right integer).
+
+def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192, compensated: bool = False):
+    """S_t = sum_x prod_j fields[t_j - 1][x] in FP64, for orders 2 to 6.
+
+    The grid is summed in chunks.  Each tuple is split into a left and a right
+    part -- a shell and a shell (order 2), a pair and a shell (3), a pair and a
+    pair (4), a pair and a triple (5), a triple and a triple (6) -- whose products
+    d_i d_j (d_k) are formed once per chunk and multiplied with a matrix product.
+    With compensated=True the chunk results are added with error-free
+    transformations and the pair (hi, lo) with S = hi + lo is returned (used for
+    polygon counts, which reach 10^12 and must round to the right integer).
     """
     tuples = np.asarray(tuples, dtype=np.int64)
     order = tuples.shape[1]
+    if order not in (2, 3, 4, 5, 6):
+        raise ValueError("product_sums supports orders 2 to 6")
     nb = fields.shape[0]
     flat = fields.reshape(nb, -1)
     G = flat.shape[1]
-    pairs = pair_list(nb)
-    pidx = {(int(i), int(j)): n for n, (i, j) in enumerate(pairs)}
-    if order == 2:
-        shape = (nb, nb)
-    elif order == 3:
-        shape = (len(pairs), nb)
-    elif order == 4:
-        shape = (len(pairs), len(pairs))
-    else:
-        raise ValueError("product_sums supports orders 2, 3 and 4")
-    acc = np.zeros(shape)
-    lo = np.zeros(shape) if compensated else None
-    pi = pairs[:, 0] - 1
-    pj = pairs[:, 1] - 1
+    left = {2: 1, 3: 2, 4: 2, 5: 2, 6: 3}[order]     # factors in the left part
+    lists = {1: sorted_tuples(1, nb), 2: pair_list(nb), 3: triple_list(nb)}
+    lrows, rrows = lists[left], lists[order - left]
+    lidx = {tuple(int(v) for v in r): n for n, r in enumerate(lrows)}
+    ridx = {tuple(int(v) for v in r): n for n, r in enumerate(rrows)}
+    acc = np.zeros((len(lrows), len(rrows)))
+    lo = np.zeros_like(acc) if compensated else None
+
+    def products(blk, rows):
+        out = blk[rows[:, 0] - 1].copy()
+        for c in range(1, rows.shape[1]):
+            out *= blk[rows[:, c] - 1]
+        return out
+
     for x0 in range(0, G, chunk):
         blk = flat[:, x0:x0 + chunk]
-        if order == 2:
-            part = blk @ blk.T
-        else:
-            P = blk[pi] * blk[pj]
-            part = P @ blk.T if order == 3 else P @ P.T
+        L = products(blk, lrows)
+        R = L if rrows is lrows else products(blk, rrows)
+        part = L @ R.T
         if compensated:      # two-sum: acc + part = s + err exactly
             s_ = acc + part
             bb = s_ - acc
@@ -267,17 +274,9 @@ def product_sums(fields: np.ndarray, tuples: np.ndarray, chunk: int = 8192, comp
             acc = s_
         else:
             acc += part
-
-    def pick(a):
-        if order == 2:
-            return a[tuples[:, 0] - 1, tuples[:, 1] - 1]
-        rows = np.array([pidx[(int(u), int(v))] for u, v in tuples[:, :2]], dtype=np.int64)
-        if order == 3:
-            return a[rows, tuples[:, 2] - 1]
-        cols = np.array([pidx[(int(u), int(v))] for u, v in tuples[:, 2:]], dtype=np.int64)
-        return a[rows, cols]
-
-    return (pick(acc), pick(lo)) if compensated else pick(acc)
+    rows = np.array([lidx[tuple(int(v) for v in t[:left])] for t in tuples], dtype=np.int64)
+    cols = np.array([ridx[tuple(int(v) for v in t[left:])] for t in tuples], dtype=np.int64)
+    return (acc[rows, cols], lo[rows, cols]) if compensated else acc[rows, cols]
 
 
 def tuple_product_sums(fields_by_shell: dict, tuples) -> np.ndarray:
@@ -336,42 +335,61 @@ def pair_counts(c_i: np.ndarray, c_j: np.ndarray) -> np.ndarray:
     return R.astype(np.int64)
 
 
-def polygon_counts_exact(N: int, order: int, n_shells: int, width: float, tuples) -> np.ndarray:
-    """The counts of polygon_counts, summed in integers from pair counts.
+def triple_counts(c_i: np.ndarray, c_j: np.ndarray, c_k: np.ndarray) -> np.ndarray:
+    """T_ijk(q) = #{(q_1, q_2, q_3) in S_i x S_j x S_k : q_1 + q_2 + q_3 = q mod N}, rfftn layout.
 
-    A closed ordered tuple q_1 + ... + q_n = 0 (mod N) splits as q_1 + q_2 = q and
-    q_3 (+ q_4) = -q, so n_ijk = sum_{q in S_k} P_ij(q) and n_ijkl = sum_q P_ij(q) P_kl(q)
-    (P_ij is even because every shell is); order 2 is P_ij(0).  Nothing large is
-    ever rounded, so the result is exact for any count that fits in int64.
+    As for pair_counts: the DFT of c_i c_j c_k is N^3 T_ijk, and every value is an
+    integer no larger than |S_i| |S_j|, small enough for the FP64 transform to be
+    rounded to it exactly.
+    """
+    N = c_i.shape[0]
+    T = rfftn(c_i * c_j * c_k)
+    T /= float(N) ** 3
+    R = np.rint(T.real)
+    if np.abs(T.real - R).max() >= 1e-3 or np.abs(T.imag).max() >= 1e-3:
+        raise ArithmeticError("triple count not integral")
+    return R.astype(np.int64)
+
+
+def polygon_counts_exact(N: int, order: int, n_shells: int, width: float, tuples) -> np.ndarray:
+    """The counts of polygon_counts, summed in integers from pair and triple counts.
+
+    A closed ordered tuple q_1 + ... + q_n = 0 (mod N) splits into a left part
+    with sum q and a right part with sum -q, so n_ijk = sum_{q in S_k} P_ij(q),
+    n_ijkl = sum_q P_ij(q) P_kl(q), n_ijklm = sum_q P_ij(q) T_klm(q) and
+    n_ijklmn = sum_q T_ijk(q) T_lmn(q) (the partial counts are even because every
+    shell is); order 2 is P_ij(0).  Nothing large is ever rounded, so the result is
+    exact for any count that fits in int64.
     """
     tuples = np.asarray(tuples, dtype=np.int64)
     order = tuples.shape[1]
-    if order not in (2, 3, 4):
-        raise ValueError("polygon_counts_exact supports orders 2, 3 and 4")
+    if order not in (2, 3, 4, 5, 6):
+        raise ValueError("polygon_counts_exact supports orders 2 to 6")
     wz = np.full(N // 2 + 1, 2, dtype=np.int64)      # half-spectrum multiplicity of q_z
     wz[0] = 1
     wz[N // 2] = 1
-    paired = sorted({int(s) for s in tuples[:, :2].ravel()} |
-                    ({int(s) for s in tuples[:, 2:].ravel()} if order == 4 else set()))
-    c = dict(zip(paired, count_fields(N, n_shells, width, paired)))
+    used = sorted({int(s) for s in tuples.ravel()})
+    c = dict(zip(used, count_fields(N, n_shells, width, used)))
     sid = shell_id_grid(N, n_shells, width) if order == 3 else None
     cache = {}
 
-    def P(i, j):
-        key = (min(i, j), max(i, j))
+    def part(shells):
+        key = tuple(sorted(shells))
         if key not in cache:
-            cache[key] = pair_counts(c[key[0]], c[key[1]])
+            cache[key] = (pair_counts(c[key[0]], c[key[1]]) if len(key) == 2
+                          else triple_counts(c[key[0]], c[key[1]], c[key[2]]))
         return cache[key]
 
     out = np.empty(len(tuples), dtype=np.int64)
     for n, t in enumerate(tuples.tolist()):
         if order == 2:
-            out[n] = P(t[0], t[1])[0, 0, 0]
+            out[n] = part(t)[0, 0, 0]
         elif order == 3:
             m = sid == t[2]
-            out[n] = int(np.sum(P(t[0], t[1])[m] * np.broadcast_to(wz, m.shape)[m]))
+            out[n] = int(np.sum(part(t[:2])[m] * np.broadcast_to(wz, m.shape)[m]))
         else:
-            out[n] = int(np.sum(P(t[0], t[1]) * P(t[2], t[3]) * wz))
+            split = 3 if order == 6 else 2
+            out[n] = int(np.sum(part(t[:split]) * part(t[split:]) * wz))
     return out
 
 

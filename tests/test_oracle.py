@@ -2,7 +2,7 @@
 
 * exact lattice counts from the sum-of-three-squares theta series,
 * direct n-gon enumeration (the estimator's definition, Sec. 2),
-* the pair-sum rule for triangle counts,
+* the pair-sum rule for triangle counts and its recursion to orders 4 to 6,
 * the n = 2 reduction to the shell-averaged |delta_hat|^2 (Parseval),
 * the unit spectrum giving a unit polyspectrum (Sec. 4: counting by delta(k) = 1),
 * homogeneity, translation and lattice symmetry,
@@ -77,6 +77,51 @@ def test_fft_estimator_equals_direct_enumeration(order, nb, width):
                                atol=1e-12 * np.abs(r["B"]).max())
 
 
+# Orders 5 and 6 (Sec. 4.2 extends the estimator to pentagons and hexagons).  The
+# enumeration cost grows as the product of the first n - 1 shell sizes, so order 6
+# is pinned on the tuples whose first five shells hold at most 18^3 62^2 vectors.
+@pytest.mark.parametrize("N,order,nb,tuples", [
+    (16, 5, 2, None), (16, 6, 1, None), (8, 5, 2, None),
+    (8, 6, 2, [(1, 1, 1, 1, 1, 1), (1, 1, 1, 1, 1, 2), (1, 1, 1, 1, 2, 2), (1, 1, 1, 2, 2, 2)])])
+def test_high_order_estimator_equals_direct_enumeration(N, order, nb, tuples):
+    delta = fieldgen.gaussian_field(N, 20 + order)
+    r = O.polyspectrum(delta, order, nb, 1.0, allow_aliasing=True)
+    cand = [tuple(t) for t in r["candidates"].tolist()]
+    pick = np.arange(len(cand)) if tuples is None else np.array([cand.index(t) for t in tuples])
+    t = r["candidates"][pick]
+    cnt, sums = O.bruteforce_polyspectrum(delta, order, nb, 1.0, t)
+    assert np.array_equal(cnt, r["candidate_counts"][pick])
+    assert np.array_equal(cnt, O.polygon_counts_exact(N, order, nb, 1.0, t))
+    assert np.all(cnt > 0)
+    scale = np.abs(sums).max()
+    assert np.abs(sums.imag).max() <= 1e-12 * scale
+    kept = {tuple(u): n for n, u in enumerate(r["tuples"].tolist())}
+    rows = np.array([kept[tuple(u)] for u in t.tolist()])
+    np.testing.assert_allclose(sums.real * N ** 3, r["sums"][rows], rtol=0, atol=1e-12 * scale * N ** 3)
+    np.testing.assert_allclose(sums.real / cnt, r["B"][rows], rtol=1e-10)
+
+
+@pytest.mark.parametrize("order", [4, 5, 6])
+def test_polygon_recursion_rule(order):
+    """sum_s n(t, s) = prod_j |S_{t_j}| - n(t) over (n-1)-tuples t whose vector sums always land in a shell.
+
+    Every ordered (n-1)-tuple of vectors either closes (counted by n(t)) or sums to a
+    non-zero q, and q lies in exactly one shell s when sum_j (t_j + 1/2) <= N_b + 1/2;
+    then -q in shell s closes the n-gon.  Components stay below N/2 at N = 32, so
+    closure modulo N is true closure for every tuple involved.
+    """
+    N, nb, width = 32, 9, 1.0
+    S = O.shell_mode_counts(N, nb, width)
+    heads = [t for t in O.sorted_tuples(order - 1, nb).tolist() if 2 * sum(t) + len(t) <= 2 * nb + 1]
+    assert len(heads) >= 3
+    full = sorted({tuple(sorted(h + [s])) for h in heads for s in range(1, nb + 1)})
+    n_full = dict(zip(full, O.polygon_counts(N, order, nb, width, np.array(full)).tolist()))
+    n_head = O.polygon_counts(N, order - 1, nb, width, np.array(heads)).tolist()
+    for h, nh in zip(heads, n_head):
+        tot = sum(n_full[tuple(sorted(h + [s]))] for s in range(1, nb + 1))
+        assert tot == int(np.prod([S[u - 1] for u in h])) - nh
+
+
 def test_aliased_flag_required():
     with pytest.raises(ValueError):
         O.polyspectrum(np.zeros((16, 16, 16)), 3, 6, 1.0)
@@ -146,7 +191,7 @@ def test_power_spectrum_parseval():
     np.testing.assert_array_equal(r["counts"], O.shell_mode_counts(N, nb, 1.0))
 
 
-@pytest.mark.parametrize("order,nb", [(3, 8), (4, 5)])
+@pytest.mark.parametrize("order,nb", [(3, 8), (4, 5), (5, 4), (6, 3)])
 def test_unit_spectrum_gives_unit_polyspectrum(order, nb):
     N = 32
     r = O.polyspectrum(fieldgen.unit_spectrum_field(N), order, nb, 1.0)
@@ -282,7 +327,8 @@ def test_exact_counts_match_direct_enumeration(order, nb):
     assert np.array_equal(O.polygon_counts_exact(N, order, nb, 1.0, t), cnt)
 
 
-@pytest.mark.parametrize("order,nb,width", [(3, 16, 1.0), (4, 10, 1.0), (4, 6, 2.0)])
+@pytest.mark.parametrize("order,nb,width", [(3, 16, 1.0), (4, 10, 1.0), (4, 6, 2.0), (5, 6, 1.0),
+                                            (6, 5, 1.0)])
 def test_exact_counts_match_fft_counts(order, nb, width):
     N = 64
     t = O.candidate_tuples(order, nb, O.is_alias_free(N, order, nb, width))
