@@ -162,8 +162,10 @@ def main():
 
     w = fieldgen.WORKLOADS[args.workload]
     order = w["order"]
-    if order not in (3, 4):
-        raise SystemExit("the benchmark step needs an order-3 or order-4 workload (forward + adjoint)")
+    if order not in (3, 4, 5, 6):
+        raise SystemExit("the benchmark step needs an order-3 to order-6 workload")
+    # orders 3 and 4 have the adjoint: a step is forward + backward; orders 5 and 6 forward only
+    has_backward = order in (3, 4)
     N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
     prec = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}[args.precision]
     dev = torch.device("cuda:0")
@@ -182,7 +184,7 @@ def main():
     def step():
         plan.shells(x)
         B = plan.contract()
-        return B, plan.backward(2.0 * B)
+        return B, (plan.backward(2.0 * B) if has_backward else None)
 
     for i in range(args.warmup):
         step()
@@ -211,29 +213,37 @@ def main():
     ctr_ms = avg("contract")
     adj_ms = avg("adj_gemm")
     n_pairs = nb * (nb + 1) // 2
-    n_rests = n_pairs if order == 3 else nb * (nb + 1) * (nb + 2) // 6   # products the adjoint forms
+    n_triples = nb * (nb + 1) * (nb + 2) // 6
+    n_rests = n_pairs if order == 3 else n_triples   # products the adjoint forms
     peak = PEAK_TFLOPS[args.precision]
     # algorithmic flops per launch: 2 per (closing triplet x point) + 1 per (pair x point)
     # for the contraction; 2 per (adjoint weight x point) + 1 per (pair x point) for the
     # adjoint product, whatever the tiles the kernels actually issue
     # the FP16 split of an order-3 plan runs the shell-block aligned kernel
     ctr_kernel = "contract_j3" if (args.precision == "fp16" and order == 3) else "contract_tiles"
-    # algorithmic flops: order 3, 2 per (triplet x point) + 1 per (pair x point); order 4,
-    # 2 per (quadruple x point) + 1 per (pair x point) for the two pair products
-    ctr_roof = roofline(ctr_kernel, ctr_ms, (2.0 * plan.n_closing + n_pairs) * G * batch,
+    # algorithmic flops: 2 per (closing tuple x point), plus the row products formed once
+    # per point: 1 per pair (orders 3 to 5) and 2 per triple (orders 5 and 6)
+    row_flops = (n_pairs if order <= 5 else 0) + (2 * n_triples if order >= 5 else 0)
+    ctr_roof = roofline(ctr_kernel, ctr_ms, (2.0 * plan.n_closing + row_flops) * G * batch,
                         ps.polyspec_issued_flops(plan.handle, "contract"), peak,
                         load_traffic(ctr_kernel, args.workload, args.precision))
-    n_w = adjoint_weight_entries(plan.tuples)
-    adj_roof = roofline("adjoint_gemm" if order == 3 else "adjoint4_gemm", adj_ms,
-                        (2.0 * n_w + n_rests * (order - 2)) * G * batch,
-                        ps.polyspec_issued_flops(plan.handle, "adj_gemm"), peak,
-                        load_traffic("adjoint_gemm", args.workload, args.precision))
-    dominant, other = (adj_roof, ctr_roof) if adj_ms >= ctr_ms else (ctr_roof, adj_roof)
+    if has_backward:
+        n_w = adjoint_weight_entries(plan.tuples)
+        adj_roof = roofline("adjoint_gemm" if order == 3 else "adjoint4_gemm", adj_ms,
+                            (2.0 * n_w + n_rests * (order - 2)) * G * batch,
+                            ps.polyspec_issued_flops(plan.handle, "adj_gemm"), peak,
+                            load_traffic("adjoint_gemm", args.workload, args.precision))
+        dominant, other = (adj_roof, ctr_roof) if adj_ms >= ctr_ms else (ctr_roof, adj_roof)
+    else:
+        n_w, dominant, other = None, ctr_roof, None
+    names = {3: ("bispectrum", "bin-triplets"), 4: ("trispectrum", "bin-quadruples"),
+             5: ("quadspectrum", "bin-quintuples"), 6: ("pentaspectrum", "bin-sextuples")}[order]
     out = {
         "metric": ("bispectrum bin-triplets*gridpts/s at 512^3 (split-MFMA vs FP32); fwd+bwd ms" if order == 3
-                   else "trispectrum bin-quadruples*gridpts/s (split-MFMA); fwd+bwd ms"),
+                   else f"{names[0]} {names[1]}*gridpts/s (split-MFMA); " + ("fwd+bwd ms" if has_backward
+                                                                              else "fwd ms")),
         "value": plan.n_closing * G * batch / (ms_step * 1e-3),
-        "unit": "bin-triplets*gridpts/s" if order == 3 else "bin-quadruples*gridpts/s",
+        "unit": f"{names[1]}*gridpts/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

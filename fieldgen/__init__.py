@@ -123,6 +123,12 @@ WORKLOADS = {
                               field="gaussian", seeds=list(range(40, 48)), target_seed=48),
     "bispec_512_lognormal": dict(N=512, order=3, n_shells=64, width=1.0, batch=1,
                                  field="lognormal", seeds=[5]),
+    # orders 5 and 6 (Sec. 4.2): as many unit-width shells as keep every polygon
+    # count below 2^44, the limit of exact recovery from float64 count sums
+    "quadspec_256_lognormal": dict(N=256, order=5, n_shells=16, width=1.0, batch=1,
+                                   field="lognormal", seeds=[2]),
+    "pentaspec_256_lognormal": dict(N=256, order=6, n_shells=8, width=1.0, batch=1,
+                                    field="lognormal", seeds=[2]),
 }
 
 

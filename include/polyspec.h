@@ -71,9 +71,9 @@ enum {
 
 typedef struct {
   int32_t N;            /* grid points per side; a power of two, 32 <= N <= 1024            */
-  int32_t order;        /* n = 2, 3 or 4                                                     */
+  int32_t order;        /* n = 2 to 6 (Sec. 4.2 runs the estimator up to hexagons, n = 6)  */
   int32_t n_shells;     /* N_b >= 1; (N_b + 1/2) * width <= N/2; the matrix-core contraction
-                           handles N_b <= 64                                                 */
+                           handles N_b <= 64, and N_b <= 32 at orders 5 and 6                 */
   double shell_width;   /* D > 0, in units of k_f (exact binary value is used)              */
   int32_t batch;        /* independent fields processed together, >= 1                      */
   int32_t precision;    /* polyspec_precision                                                */
@@ -101,7 +101,10 @@ polyspec_status polyspec_shells(polyspec_plan_t plan, const void* d_delta);
 /* Product sums and normalisation (Sec. 2, the grid sum of products of the I_k;
  * Appendix A, division by N^3 and by the polygon count).  Writes B_t as float64
  * [batch][n_closing] to d_out, and the raw sums S_t (float64, same shape) to
- * d_raw_sums when it is not NULL.  POLYSPEC_ERR_STATE before polyspec_shells. */
+ * d_raw_sums when it is not NULL.  The sums are matrix-core products of row
+ * products of the shell fields: shell x shell (n = 2), pair x shell (3), pair x
+ * pair (4), pair x triple (5) and triple x triple (6).  POLYSPEC_ERR_STATE before
+ * polyspec_shells. */
 polyspec_status polyspec_contract(polyspec_plan_t plan, double* d_out, double* d_raw_sums);
 
 /* Adjoint of shells + contract (not in the paper): given dL/dB_t in d_grad_out

@@ -48,11 +48,14 @@ constexpr int kCtrWaves = 16;
 constexpr int kCtrThreads = 64 * kCtrWaves;
 constexpr int kSlots = 14;       // tiles per wave (order 3)
 constexpr int kSlots4 = 10;      // tiles per wave (order 4: B rows formed too)
+constexpr int kSlots56 = 8;      // tiles per wave (order 5: triple rows formed)
+constexpr int kSlots6 = 7;       // tiles per wave (order 6: triples on both sides; 8 would spill)
 constexpr int kSlotsMax = 16;    // stride of the per-wave slot tables
 constexpr int kKStep = 64;       // grid points per LDS stage (two MFMA K-steps)
 constexpr int kRowStride = 68;   // floats per staged field row (64 + 4 pad)
 constexpr int kMaxBlk = 4;       // shell blocks of 16 (n_shells <= 64)
 constexpr int kFp16Top = 6;      // |scaled shell value| < 2^7, so pair products stay below 2^14
+constexpr int kTripleShift = 7;  // FP16: triple products (< 2^21) are scaled by 2^-7 into range
 
 template <int PREC>
 struct Operand;
@@ -122,7 +125,7 @@ __device__ __forceinline__ void load_row8(const float* lds_row, int g, float (&x
 
 
 
-__device__ __forceinline__ int fp16_shell_exp(const unsigned* absmax, int idx) {
+__device__ __forceinline__ int shell_scale_exp(const unsigned* absmax, int idx) {
   const float m = __uint_as_float(absmax[idx]);
   if (!(m > 0.f)) return 0;
   return kFp16Top - ilogbf(m);
@@ -191,6 +194,23 @@ __device__ __forceinline__ Operand<PREC> form_pair(const float* S, int uv, int g
   return make_operand<PREC>(x, 1.f);
 }
 
+// Product of NF staged shell rows (shell indices in the bytes of w), split for the
+// matrix cores.  In FP16 a triple of scaled values can reach 2^21, beyond the
+// format's range, so it enters the split scaled by 2^-kTripleShift (removed in FP64
+// with the other scale factors).
+template <int PREC, int NF>
+__device__ __forceinline__ Operand<PREC> form_rows(const float* S, int w, int g) {
+  float x[8], y[8];
+  load_row8(S + (w & 0xff) * kRowStride, g, x);
+#pragma unroll
+  for (int f = 1; f < NF; ++f) {
+    load_row8(S + ((w >> (8 * f)) & 0xff) * kRowStride, g, y);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] *= y[r];
+  }
+  return make_operand<PREC>(x, NF == 3 ? 1.0f / (1 << kTripleShift) : 1.0f);
+}
+
 // FP16 pair product straight from the split operand words of its two shell rows,
 // with packed half-precision error-free products: p_hi = fl(u_hi v_hi), its rounding
 // error e = u_hi v_hi - p_hi exactly (one fused multiply-add), and
@@ -214,18 +234,25 @@ __device__ __forceinline__ Operand<kFP16> form_pair_f16(const uint4 (*hi)[64], c
 }
 
 // ORDER 2: A = shell block, B = shell block;  ORDER 3: A = pair block, B = shell
-// block;  ORDER 4: A = pair block, B = pair block.
+// block;  ORDER 4: A = pair block, B = pair block;  ORDER 5: A = pair block, B =
+// triple block;  ORDER 6: A = triple block, B = triple block.
 //
 // A stage holds 64 grid points (two MFMA K-steps of 32).  16 waves share one stage;
-// each wave owns up to kSlotsFor<ORDER> tiles.
+// each wave owns up to slots_for<ORDER>() tiles.
 template <int ORDER>
-constexpr int slots_for() { return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : kSlots4; }
+constexpr int slots_for() { return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : ORDER == 4 ? kSlots4 : ORDER == 5 ? kSlots56 : kSlots6; }
 
 template <int PREC, int ORDER>
 __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
-  // FP16 forms pair products from the operand words alone; the other precisions
-  // form them from float32 rows staged in `stage`
-  constexpr int kStageFloats = PREC == kFP16 ? 4 : (kMaxBlk * 16 + 1) * kRowStride;
+  // FP16 up to order 4 forms pair products from the operand words alone; the other
+  // precisions, and every precision at orders 5 and 6, form their row products from
+  // float32 rows staged in `stage`
+  constexpr bool kFloatStage = PREC != kFP16 || ORDER >= 5;
+  // FP16 needs the per-shell power-of-two scaling for its range; at orders 5 and 6 every
+  // precision takes it, since unscaled products of five or six shell values summed over
+  // the grid overflow float32 (they reach 1e45 at 256^3)
+  constexpr bool kScaled = PREC == kFP16 || ORDER >= 5;
+  constexpr int kStageFloats = kFloatStage ? (kMaxBlk * 16 + 1) * kRowStride : 4;
   __shared__ __attribute__((aligned(16))) float stage[2][kStageFloats];
   // [buffer][K-step][shell block][lane]; block kMaxBlk stays zero (padding pairs)
   __shared__ uint4 opHi[2][2][kMaxBlk + 1][64];
@@ -244,17 +271,17 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
 
   for (int i = tid; i <= nrows; i += kCtrThreads) {
     float sc = 1.f;
-    if (PREC == kFP16) sc = i < p.n_shells ? ldexpf(1.0f, fp16_shell_exp(p.absmax, b * p.n_shells + i)) : 0.f;
+    if (kScaled) sc = i < p.n_shells ? ldexpf(1.0f, shell_scale_exp(p.absmax, b * p.n_shells + i)) : 0.f;
     lds_scale[i] = sc;
   }
-  if constexpr (PREC != kFP16) {
+  if constexpr (kFloatStage) {
     for (int i = tid; i < 2 * (nrows + 1) * kRowStride; i += kCtrThreads) {
       const int buf = i / ((nrows + 1) * kRowStride);
       const int rr = (i / kRowStride) % (nrows + 1);
       if (rr >= p.n_shells) stage[buf][i % ((nrows + 1) * kRowStride)] = 0.f;
     }
   }
-  for (int i = tid; i < 4 * (kMaxBlk + 1) * 64; i += kCtrThreads) {
+  for (int i = tid; ORDER <= 4 && i < 4 * (kMaxBlk + 1) * 64; i += kCtrThreads) {
     const int bh = i / ((kMaxBlk + 1) * 64), kb = (i / 64) % (kMaxBlk + 1), ln = i % 64;
     if (kb * 16 + (ln & 15) >= p.n_shells) {
       opHi[bh >> 1][bh & 1][kb][ln] = make_uint4(0, 0, 0, 0);
@@ -278,12 +305,14 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
   const int st_lane = (((st_col & 31) >> 3) << 4) | (st_row & 15);
   const int st_half = (st_col >> 2) & 1;
   auto stage_store = [&](int buf, float4 v) {
-    if (PREC == kFP16) {  // every FP16 operand works on the power-of-two scaled values
+    if (kScaled) {  // every operand works on the power-of-two scaled values
       const float sc = lds_scale[st_row];
       v = make_float4(v.x * sc, v.y * sc, v.z * sc, v.w * sc);
     }
-    if constexpr (PREC != kFP16) *reinterpret_cast<float4*>(&stage[buf][st_row * kRowStride + st_col]) = v;
-    if constexpr (PREC == kFP32) {
+    if constexpr (kFloatStage) *reinterpret_cast<float4*>(&stage[buf][st_row * kRowStride + st_col]) = v;
+    if constexpr (ORDER >= 5) {
+      // every operand is formed from the float rows
+    } else if constexpr (PREC == kFP32) {
       const uint4 w = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
                                  __float_as_uint(v.w));
       if (st_half) opLo[buf][st_h][st_kb][st_lane] = w; else opHi[buf][st_h][st_kb][st_lane] = w;
@@ -303,8 +332,9 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
   // Slot state for the whole chunk.  Uniform byte per slot (4 slots per word, in
   // SGPRs): bits 0-1 B shell block, 2-3 A shell block (order 2), 4 = form A here,
   // 7 = empty.  Per-lane shells of the lane's pair rows: order 3 packs (u, v) of
-  // two slots per word, order 4 packs (u_A, v_A, u_B, v_B) of one slot per word.
-  constexpr int NLW = ORDER == 4 ? NS : (NS + 1) / 2;
+  // two slots per word, order 4 packs (u_A, v_A, u_B, v_B) of one slot per word;
+  // orders 5 and 6 use two words per slot, the A row's shells then the B row's.
+  constexpr int NLW = ORDER == 4 ? NS : ORDER >= 5 ? 2 * NS : (NS + 1) / 2;
   const int* uni = p.slot_uni + ((size_t)group * kCtrWaves + wave) * (kSlotsMax / 4);
   int un[(NS + 3) / 4];
 #pragma unroll
@@ -327,6 +357,12 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
       for (int s = 0; s < NS; ++s) {
         const int info = (un[s / 4] >> (8 * (s % 4))) & 0xff;
         if (info & 0x80) break;
+        if constexpr (ORDER >= 5) {
+          if (info & 0x10) A = form_rows<PREC, ORDER == 6 ? 3 : 2>(S + 32 * h, lv[2 * s], g);
+          const Operand<PREC> Bop = form_rows<PREC, 3>(S + 32 * h, lv[2 * s + 1], g);
+          mma<PREC>(acc[s], A, Bop);
+          continue;
+        }
         if (ORDER == 2) {
           const int ab = (info >> 2) & 3;
           A = op_from_words<PREC>(opHi[cur][h][ab][lane], opLo[cur][h][ab][lane]);
@@ -376,6 +412,10 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
 // ---------------------------------------------------------------------------
 constexpr int kJThreads = 64 * kJWaves;
 static_assert(jslot(7, 3, 3) + 1 == kJSlots, "slot numbering");
+static_assert(kSlots == kSlotsHost && kSlots4 == kSlots4Host && kSlots56 == kSlots56Host && kSlots6 == kSlots6Host &&
+                  kSlotsMax == kSlotsMaxHost && 2 * kSlots56 <= kSlotsMax && kMaxBlk == kMaxBlkHost &&
+                  kCtrWaves == kCtrWavesHost,
+              "host and device tile tables agree");
 
 __device__ __forceinline__ Operand<kFP16> pair_f16(const Operand<kFP16>& a, const Operand<kFP16>& b) {
   Operand<kFP16> o;
@@ -399,7 +439,7 @@ __global__ __launch_bounds__(kJThreads, 1) void contract_j3(CtrJParams p) {
   const int b = blockIdx.z;
 
   for (int i = tid; i < kMaxBlk * 16; i += kJThreads)
-    lds_scale[i] = i < p.n_shells ? ldexpf(1.0f, fp16_shell_exp(p.absmax, b * p.n_shells + i)) : 0.f;
+    lds_scale[i] = i < p.n_shells ? ldexpf(1.0f, shell_scale_exp(p.absmax, b * p.n_shells + i)) : 0.f;
   for (int i = tid; i < 4 * kMaxBlk * 64; i += kJThreads) {
     const int bh = i / (kMaxBlk * 64), kb = (i / 64) % kMaxBlk, ln = i % 64;
     if (kb * 16 + (ln & 15) >= p.n_shells) {
@@ -567,10 +607,11 @@ __global__ void gather_normalize(const double* __restrict__ tmp, int n_groups, l
   const double* src = tmp + (size_t)b * n_groups * n_ent;
   double s = 0.0;
   for (int grp = 0; grp < n_groups; ++grp) s += src[(size_t)grp * n_ent + e];
-  if (prec == kFP16) {
+  if (prec == kFP16 || order >= 5) {   // the scaling of the contraction's operands
     int ex = 0;
-    for (int j = 0; j < order; ++j) ex += fp16_shell_exp(absmax, b * n_shells + bins[t * order + j]);
-    s = ldexp(s, -ex);
+    for (int j = 0; j < order; ++j) ex += shell_scale_exp(absmax, b * n_shells + bins[t * order + j]);
+    const int triples = prec != kFP16 ? 0 : order == 5 ? 1 : order == 6 ? 2 : 0;   // FP16 triple operands
+    s = ldexp(s, triples * kTripleShift - ex);
   }
   const double B = s * fnorm[t];
   out[(size_t)b * n_closing + t] = B;
@@ -1140,8 +1181,14 @@ hipError_t launch_contract(int prec, int order, const CtrParams& p, int n_groups
     if (prec == kFP32) L(kFP32, 2); else if (prec == kBF16) L(kBF16, 2); else L(kFP16, 2);
   } else if (order == 3) {
     if (prec == kFP32) L(kFP32, 3); else if (prec == kBF16) L(kBF16, 3); else L(kFP16, 3);
-  } else {
+  } else if (order == 4) {
     if (prec == kFP32) L(kFP32, 4); else if (prec == kBF16) L(kBF16, 4); else L(kFP16, 4);
+  } else if (order == 5) {
+    if (prec == kFP32) L(kFP32, 5); else if (prec == kBF16) L(kBF16, 5); else L(kFP16, 5);
+  } else if (order == 6) {
+    if (prec == kFP32) L(kFP32, 6); else if (prec == kBF16) L(kBF16, 6); else L(kFP16, 6);
+  } else {
+    return hipErrorInvalidValue;
   }
 #undef L
   return hipGetLastError();
@@ -1189,9 +1236,17 @@ hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, co
   else if (order == 3)
     hipLaunchKernelGGL(counts_wedge<3>, grid, dim3(kCntThreads), shm, st, cw, nwedge, wmult, cand, n_cand, n_shells,
                        stages_per_chunk, part);
-  else
+  else if (order == 4)
     hipLaunchKernelGGL(counts_wedge<4>, grid, dim3(kCntThreads), shm, st, cw, nwedge, wmult, cand, n_cand, n_shells,
                        stages_per_chunk, part);
+  else if (order == 5)
+    hipLaunchKernelGGL(counts_wedge<5>, grid, dim3(kCntThreads), shm, st, cw, nwedge, wmult, cand, n_cand, n_shells,
+                       stages_per_chunk, part);
+  else if (order == 6)
+    hipLaunchKernelGGL(counts_wedge<6>, grid, dim3(kCntThreads), shm, st, cw, nwedge, wmult, cand, n_cand, n_shells,
+                       stages_per_chunk, part);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

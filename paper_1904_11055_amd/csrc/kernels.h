@@ -52,6 +52,9 @@ struct CtrParams {
 constexpr int kCtrWavesHost = 16;
 constexpr int kSlotsHost = 14;
 constexpr int kSlots4Host = 10;
+constexpr int kSlots56Host = 8;
+constexpr int kSlots6Host = 7;
+constexpr int kMaxShells56 = 32;    // orders 5 and 6: shells per plan (row tables stay small)
 constexpr int kSlots2Host = 4;
 constexpr int kSlotsMaxHost = 16;   // per-wave stride of the slot tables
 constexpr int kStagePtsHost = 64;

@@ -347,11 +347,45 @@ struct TileKey {
 // lane 16 (row / 4) + col, register row % 4.
 inline int tile_entry(int row, int col) { return 4 * (16 * (row / 4) + col) + (row % 4); }
 
+// Triples (i <= j <= k) for the row blocks of orders 5 and 6, packed as shell bytes
+// i | j << 8 | k << 16, padded with the zero row.  The B side is ordered by its
+// smallest shell (then j, k) and the A side of order 6 by its largest (then j, i):
+// the needed tuples pair an A row whose largest shell is at most the B row's
+// smallest, so both orders keep the needed tiles in a dense staircase.
+void build_triples(const polyspec_plan_s* p, bool by_largest, std::vector<int>* rows, std::vector<int>* tidx) {
+  const int nb = p->nb, zrow = p->n_blk * 16;
+  rows->clear();
+  tidx->assign((size_t)nb * nb * nb, -1);
+  std::vector<std::array<int, 3>> tl;
+  for (int i = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j)
+      for (int k = j; k < nb; ++k) tl.push_back({i, j, k});
+  if (by_largest)
+    std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 3>& a, const std::array<int, 3>& b) {
+      return a[2] != b[2] ? a[2] < b[2] : a[1] != b[1] ? a[1] < b[1] : a[0] < b[0];
+    });
+  for (const auto& t : tl) {
+    (*tidx)[((size_t)t[0] * nb + t[1]) * nb + t[2]] = (int)rows->size();
+    rows->push_back(t[0] | (t[1] << 8) | (t[2] << 16));
+  }
+  while (rows->size() % 16) rows->push_back(zrow | (zrow << 8) | (zrow << 16));
+}
+
 polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
   std::vector<int> pidx;
   build_pairs(p, &pidx);
   const int n = p->order, nb = p->nb;
   const size_t nc = p->cand.size() / n;
+  // shell bytes of every A and B row (orders 5 and 6)
+  std::vector<int> arows, brows, aidx, bidx;
+  if (n >= 5) {
+    build_triples(p, false, &brows, &bidx);
+    if (n == 6) {
+      build_triples(p, true, &arows, &aidx);
+    } else {
+      for (int w : p->pair_uv) arows.push_back((w & 0xff) | (((w >> 16) & 0xff) << 8));
+    }
+  }
   std::map<TileKey, int> tiles;
   std::vector<std::array<int, 4>> loc(nc);  // ablk, bblk, row, col
   for (size_t c = 0; c < nc; ++c) {
@@ -363,9 +397,15 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
     } else if (n == 3) {
       ra = pidx[t[0] * nb + t[1]];
       rb = t[2];
-    } else {
+    } else if (n == 4) {
       ra = pidx[t[0] * nb + t[1]];
       rb = pidx[t[2] * nb + t[3]];
+    } else if (n == 5) {
+      ra = pidx[t[0] * nb + t[1]];
+      rb = bidx[((size_t)t[2] * nb + t[3]) * nb + t[4]];
+    } else {
+      ra = aidx[((size_t)t[0] * nb + t[1]) * nb + t[2]];
+      rb = bidx[((size_t)t[3] * nb + t[4]) * nb + t[5]];
     }
     loc[c] = {ra / 16, rb / 16, ra % 16, rb % 16};
     tiles[TileKey{ra / 16, rb / 16}] = 0;
@@ -383,7 +423,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
     (*ent_of_cand)[c] = t * 256 + tile_entry(loc[c][2], loc[c][3]);
   }
   // units: runs of tiles sharing the A block, cut into pieces that fit one wave
-  const int cap = n == 2 ? ps::kSlots2Host : n == 3 ? ps::kSlotsHost : ps::kSlots4Host;
+  const int cap = n == 2 ? ps::kSlots2Host : n == 3 ? ps::kSlotsHost : n == 4 ? ps::kSlots4Host : n == 5 ? ps::kSlots56Host : ps::kSlots6Host;
   std::vector<std::pair<int, int>> units;  // [first tile, count]
   for (int t = 0; t < id;) {
     int u = t;
@@ -415,7 +455,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
       best = &groups.back()[0];
     }
     for (int k = 0; k < cnt; ++k) best->tiles.push_back(units[ui].first + k);
-    best->load += 1.0 + cnt * (n == 4 ? 2.0 : 1.0);   // one A formation + the tiles
+    best->load += 1.0 + cnt * (n >= 5 ? 3.0 : n == 4 ? 2.0 : 1.0);   // one A formation + the tiles
   }
   p->n_groups = (int)groups.size();
   // slot tables (see contract_tiles): a uniform byte per slot and per-lane pair shells,
@@ -444,12 +484,16 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
           const TileKey k = tlist[tl[s]];
           const int form = k.a != prev_a ? 1 : 0;
           prev_a = k.a;
-          info = (n == 4 ? 0 : (k.b & 3)) | (n == 2 ? (k.a & 3) << 2 : 0) | (form << 4);
+          info = (n >= 4 ? 0 : (k.b & 3)) | (n == 2 ? (k.a & 3) << 2 : 0) | (form << 4);
           slot_tile[gw * S + s] = tl[s];
           for (int r = 0; r < 16; ++r) {
-            int& word = lanew[(gw * 16 + r) * S + (n == 4 ? s : s / 2)];
-            if (n == 3) word |= uv8(16 * k.a + r) << (16 * (s % 2));
-            if (n == 4) word = uv8(16 * k.a + r) | (uv8(16 * k.b + r) << 16);
+            int* row_words = &lanew[(gw * 16 + r) * S];
+            if (n == 3) row_words[s / 2] |= uv8(16 * k.a + r) << (16 * (s % 2));
+            if (n == 4) row_words[s] = uv8(16 * k.a + r) | (uv8(16 * k.b + r) << 16);
+            if (n >= 5) {
+              row_words[2 * s] = arows[16 * k.a + r];
+              row_words[2 * s + 1] = brows[16 * k.b + r];
+            }
           }
         }
         uni[gw * (S / 4) + s / 4] |= info << (8 * (s % 4));
@@ -632,7 +676,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   const polyspec_desc& d = p->desc;
   if (d.N < 32 || d.N > 1024 || (d.N & (d.N - 1)) != 0)
     return p->fail(POLYSPEC_ERR_INVALID_ARG, "N must be a power of two in [32, 1024]");
-  if (d.order < 2 || d.order > 4) return p->fail(POLYSPEC_ERR_INVALID_ARG, "order must be 2, 3 or 4");
+  if (d.order < 2 || d.order > 6) return p->fail(POLYSPEC_ERR_INVALID_ARG, "order must be 2 to 6");
   if (d.n_shells < 1) return p->fail(POLYSPEC_ERR_INVALID_ARG, "n_shells must be >= 1");
   if (d.batch < 1) return p->fail(POLYSPEC_ERR_INVALID_ARG, "batch must be >= 1");
   if (d.precision < 0 || d.precision > 2) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown precision");
@@ -663,6 +707,8 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   }
   if (d.n_shells > 16 * ps::kMaxBlkHost)
     return p->fail(POLYSPEC_ERR_UNSUPPORTED, "the matrix-core contraction handles at most 64 shells");
+  if (d.order >= 5 && d.n_shells > ps::kMaxShells56)
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "orders 5 and 6 handle at most 32 shells");
   if ((d.flags & POLYSPEC_INPUT_HALF_SPECTRUM) && (d.N * (size_t)d.N * (d.N / 2 + 1)) == 0)
     return p->fail(POLYSPEC_ERR_INVALID_ARG, "bad half-spectrum size");
 
@@ -881,6 +927,10 @@ polyspec_status polyspec_set_precision(polyspec_plan_t p, int32_t precision) {
   return POLYSPEC_OK;
 }
 
+// The contraction scales every shell field by a power of two (from its largest
+// magnitude) for the FP16 split, and at orders 5 and 6 for every precision.
+static bool scaled_contraction(const polyspec_plan_s* p) { return p->prec == POLYSPEC_SPLIT_FP16 || p->order >= 5; }
+
 polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
   if (!d_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null input");
@@ -897,7 +947,7 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
                                        (const cplx<float>*)p->tw32.p, gin, p->batch, st));
   }
   Geom gs = make_geom(p, p->nb, 1);
-  const bool want_max = p->prec == POLYSPEC_SPLIT_FP16;
+  const bool want_max = scaled_contraction(p);
   if (want_max) PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
   PS_TIMED(p, POLYSPEC_PH_SHELL_P1, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
                                             (const cplx<float>*)p->tw32.p, gs, nz, st));
@@ -940,7 +990,7 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_contract before polyspec_shells");
   hipStream_t st = p->stream;
-  if (p->prec == POLYSPEC_SPLIT_FP16 && !p->absmax_valid) {  // precision switched after polyspec_shells
+  if (scaled_contraction(p) && !p->absmax_valid) {  // precision switched after polyspec_shells
     const int nz = p->batch * p->nb;
     PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
     PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));

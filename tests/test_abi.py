@@ -34,13 +34,15 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(N=100), 1), (dict(N=16), 1), (dict(N=2048), 1), (dict(order=5), 1), (dict(order=1), 1),
+    (dict(N=100), 1), (dict(N=16), 1), (dict(N=2048), 1), (dict(order=7), 1), (dict(order=1), 1),
     (dict(n_shells=0), 1), (dict(shell_width=0.0), 1), (dict(shell_width=float("nan")), 1),
     (dict(shell_width=0.1), 1), (dict(batch=0), 1), (dict(precision=3), 1),
     (dict(box_length=-1.0), 1), (dict(flags=1 << 10), 1),
     (dict(n_shells=40), 1),                      # outer edge beyond Nyquist at N = 64
     (dict(n_shells=21), 2),                      # 3 * 21.5 > 64: aliasing without the flag
     (dict(N=512, n_shells=80, shell_width=1.0), 7),  # more shells than the tile kernels hold
+    (dict(order=5, N=256, n_shells=40), 7),      # orders 5 and 6 hold at most 32 shells
+    (dict(order=6, n_shells=16), 2),             # 6 * 16.5 > 64
 ])
 def test_plan_rejects_bad_descriptors(kw, status):
     args = dict(N=64, order=3, n_shells=16, shell_width=1.0, batch=1, precision=0, box_length=0.0, flags=0)

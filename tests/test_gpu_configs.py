@@ -126,6 +126,70 @@ def test_trispec_256_lognormal(gpu, precision, tol):
     plan.close()
 
 
+def _recursion_check(plan, N, order, nb, width):
+    """sum_s n(t, s) = prod_j |S_{t_j}| - n(t) for (n-1)-tuples t whose vector sums always land in a shell.
+
+    n(t) comes from an order n-1 plan on the same grid; the identity holds at any size.
+    """
+    import paper_1904_11055_amd as ps
+    lower = ps.Plan(N, order - 1, nb, width, device="cuda:0")
+    n_low = {tuple(int(v) for v in t): int(c) for t, c in zip(lower.tuples, lower.counts)}
+    lower.close()
+    table = {tuple(int(v) for v in t): int(c) for t, c in zip(plan.tuples, plan.counts)}
+    S = O.shell_mode_counts(N, nb, width)
+    checked = 0
+    for h in itertools.combinations_with_replacement(range(1, nb + 1), order - 1):
+        if 2 * sum(h) + len(h) > 2 * nb + 1:
+            continue
+        tot = sum(table.get(tuple(sorted(h + (s,))), 0) for s in range(1, nb + 1))
+        assert tot == int(np.prod([S[u - 1] for u in h])) - n_low.get(h, 0), h
+        checked += 1
+    assert checked > 0
+
+
+# Orders 5 and 6: the sampled tuples are checked on the raw sums (relative L2) and on
+# each tuple's error relative to its term magnitude sum_x |prod d|, because a tuple
+# with few polygons is a small residual of cancelling products.  The rounding of the
+# float32 shell fields enters each of the n factors, so the gates stated for n = 3
+# are scaled by n / 3.
+@pytest.mark.parametrize("name,shells", [("quadspec_256_lognormal", [1, 2, 8, 15, 16]),
+                                         ("pentaspec_256_lognormal", [1, 2, 5, 7, 8])])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-4)])
+def test_high_order_256_lognormal(gpu, name, shells, precision, tol):
+    import torch
+    import paper_1904_11055_amd as ps
+    w = fieldgen.WORKLOADS[name]
+    N, order, nb, width = w["N"], w["order"], w["n_shells"], w["width"]
+    say(f"generating the {N}^3 lognormal field")
+    fields = _fields_cached(name)
+    plan = ps.Plan(N, order, nb, width, precision=precision, device="cuda:0")
+    plan.shells(torch.from_numpy(fields).to("cuda:0"))
+    B, S = (a.cpu().numpy()[0] for a in plan.contract(raw=True))
+    _, quot = plan.candidates()
+    assert _integral(quot)
+    _recursion_check(plan, N, order, nb, width)
+    sample = _sample(plan.tuples, order, shells)
+    say(f"oracle on {len(sample)} sampled tuples of order {order}")
+    key = (name, tuple(shells))
+    if key not in _ORACLE_CACHE:
+        dhat = O.polyspec.rfftn(fields[0].astype(np.float64))
+        d = O.shell_fields_from_hat(dhat, N, nb, width, shells)
+        by_shell = {s: d[n] for n, s in enumerate(shells)}
+        _ORACLE_CACHE[key] = (O.polygon_counts_exact(N, order, nb, width, sample),
+                              O.tuple_product_sums(by_shell, sample),
+                              O.tuple_product_sums({s: np.abs(v) for s, v in by_shell.items()}, sample))
+    n_ref, S_ref, A_ref = _ORACLE_CACHE[key]
+    idx = {tuple(int(v) for v in t): n for n, t in enumerate(plan.tuples)}
+    sel = [idx[t] for t in sample]
+    assert np.array_equal(plan.counts[sel], n_ref)
+    rel = np.linalg.norm(S[sel] - S_ref) / np.linalg.norm(S_ref)
+    scaled = np.max(np.abs(S[sel] - S_ref) / A_ref)
+    say(f"order {order}: relative L2 of the sums {rel:.2e}, largest magnitude-scaled error {scaled:.2e}")
+    assert rel < tol * order / 3
+    assert scaled < tol * order / 3
+    plan.close()
+
+
 def test_bispec_grad_128x8(gpu):
     """Batch of 8 Gaussian fields, loss sum_t (B_t - T_t)^2 with T from a ninth field."""
     import torch

@@ -117,6 +117,51 @@ def test_trispectrum(gpu, precision, tol):
     plan.close()
 
 
+# Orders 5 and 6 (Sec. 4.2 runs the estimator for pentagons and hexagons): pair x
+# triple and triple x triple tiles, alias-free at 64^3 and aliased at 32^3.
+#
+# At these orders a tuple with few polygons has a sum S_t that is a small residual
+# of large cancelling products (sum_x |prod d| / |S_t| reaches 6e4 here), so any
+# float32 evaluation misses such B_t by that factor times the rounding unit, and a
+# relative L2 over B is dominated by them.  The gates are therefore the relative L2
+# over the raw sums and the error of every tuple relative to its term magnitude
+# A_t = sum_x |prod_j d_{t_j}[x]|, each scaled by n / 3 from the gates stated for
+# n = 3, since the rounding of the float32 shell fields enters each of the n factors.
+_HIGH = {}
+
+
+def _high_ref(N, order, nb, aliased):
+    key = (N, order, nb)
+    if key not in _HIGH:
+        delta = fieldgen.lognormal_field(N, 30 + order).astype(np.float32)
+        ref = O.polyspectrum(delta.astype(np.float64), order, nb, 1.0, allow_aliasing=aliased, return_fields=True)
+        ref["magnitude"] = O.product_sums(np.abs(ref.pop("fields")), ref["tuples"])
+        _HIGH[key] = (delta, ref)
+    return _HIGH[key]
+
+
+@pytest.mark.parametrize("N,order,nb,aliased", [(64, 5, 12, False), (32, 5, 6, True), (64, 6, 8, False),
+                                                (32, 6, 5, True)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-4)])
+def test_orders_five_and_six(gpu, N, order, nb, aliased, precision, tol):
+    ps = _ps()
+    delta, ref = _high_ref(N, order, nb, aliased)
+    plan, B, S = _run(delta, order, nb, 1.0, precision=precision, flags=ps.ALLOW_ALIASING if aliased else 0)
+    assert np.array_equal(plan.tuples, ref["tuples"])
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(S[0], ref["sums"]) < tol * order / 3
+    assert np.max(np.abs(S[0] - ref["sums"]) / ref["magnitude"]) < tol * order / 3
+    np.testing.assert_allclose(B[0], S[0] / (float(N) ** 3 * ref["counts"]), rtol=1e-14)
+    plan.close()
+
+
+@pytest.mark.parametrize("order,nb", [(5, 4), (6, 3)])
+def test_unit_spectrum_gives_one_high_orders(gpu, order, nb):
+    plan, B, _ = _run(fieldgen.unit_spectrum_field(32), order, nb, 1.0)
+    np.testing.assert_allclose(B[0], 1.0, rtol=1e-5)
+    plan.close()
+
+
 @pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
 def test_aliased_configuration(gpu, precision, tol):
     ps = _ps()
