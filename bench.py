@@ -164,18 +164,30 @@ def main():
     order = w["order"]
     if order not in (3, 4, 5, 6):
         raise SystemExit("the benchmark step needs an order-3 to order-6 workload")
-    # orders 3 and 4 have the adjoint: a step is forward + backward; orders 5 and 6 forward only
-    has_backward = order in (3, 4)
+    # orders 3 and 4 have the adjoint: a step is forward + backward; orders 5 and 6, and
+    # streamed plans (which keep no whole shell fields), forward only
+    streamed = bool(w.get("stream"))
+    has_backward = order in (3, 4) and not streamed
     N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
     prec = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}[args.precision]
     dev = torch.device("cuda:0")
-    log(f"generating {args.workload} fields")
-    fields = fieldgen.workload_fields(args.workload, dtype=np.float32)
-    x = torch.from_numpy(fields).to(dev)
+    flags = ps.STREAM_SLABS if streamed else 0
+    if w.get("spectrum_of"):
+        # the input is a half spectrum: the interpolation of a smaller workload's field
+        log(f"generating the {w['spectrum_of']} field and its {N}^3 half spectrum")
+        fields = fieldgen.workload_fields(w["spectrum_of"], dtype=np.float32)
+        kc = int(np.ceil((nb + 0.5) * width)) - 1
+        x = torch.from_numpy(fieldgen.zero_padded_half_spectrum(fields[0], N, kc)[None]).to(dev)
+        flags |= ps.INPUT_HALF_SPECTRUM
+    else:
+        log(f"generating {args.workload} fields")
+        fields = fieldgen.workload_fields(args.workload, dtype=np.float32)
+        x = torch.from_numpy(fields).to(dev)
     torch.cuda.synchronize()
     log("building plan (float64 polygon counts)")
     t0 = time.perf_counter()
-    plan = ps.Plan(N, order, nb, width, batch=batch, precision=prec, device=dev)
+    plan = ps.Plan(N, order, nb, width, batch=batch, precision=prec, flags=flags, device=dev)
+    launches = N // plan.slab_planes      # contraction launches per step (slabs when streamed)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     log(f"plan built in {plan_s:.2f} s: {plan.n_closing} closing tuples")
@@ -208,8 +220,11 @@ def main():
 
     fwd = ["input_q3", "input_q2", "input_q1", "shell_p1", "shell_p2", "shell_p3", "contract", "reduce", "gather"]
     bwd = ["adj_weights", "adj_gemm", "adj_q3", "adj_q2", "adj_q1", "grad_p1", "grad_p2", "grad_p3"]
-    fwd_ms = sum(avg(k) for k in fwd)
-    bwd_ms = sum(avg(k) for k in bwd)
+    def per_step(name):   # a streamed step launches the slab kernels once per slab
+        return prof[name][0] / args.steps
+
+    fwd_ms = sum(per_step(k) for k in fwd)
+    bwd_ms = sum(per_step(k) for k in bwd)
     ctr_ms = avg("contract")
     adj_ms = avg("adj_gemm")
     n_pairs = nb * (nb + 1) // 2
@@ -224,8 +239,8 @@ def main():
     # algorithmic flops: 2 per (closing tuple x point), plus the row products formed once
     # per point: 1 per pair (orders 3 to 5) and 2 per triple (orders 5 and 6)
     row_flops = (n_pairs if order <= 5 else 0) + (2 * n_triples if order >= 5 else 0)
-    ctr_roof = roofline(ctr_kernel, ctr_ms, (2.0 * plan.n_closing + row_flops) * G * batch,
-                        ps.polyspec_issued_flops(plan.handle, "contract"), peak,
+    ctr_roof = roofline(ctr_kernel, ctr_ms, (2.0 * plan.n_closing + row_flops) * G * batch / launches,
+                        ps.polyspec_issued_flops(plan.handle, "contract") / launches, peak,
                         load_traffic(ctr_kernel, args.workload, args.precision))
     if has_backward:
         n_w = adjoint_weight_entries(plan.tuples)
@@ -239,9 +254,11 @@ def main():
     names = {3: ("bispectrum", "bin-triplets"), 4: ("trispectrum", "bin-quadruples"),
              5: ("quadspectrum", "bin-quintuples"), 6: ("pentaspectrum", "bin-sextuples")}[order]
     out = {
-        "metric": ("bispectrum bin-triplets*gridpts/s at 512^3 (split-MFMA vs FP32); fwd+bwd ms" if order == 3
-                   else f"{names[0]} {names[1]}*gridpts/s (split-MFMA); " + ("fwd+bwd ms" if has_backward
-                                                                              else "fwd ms")),
+        "metric": ("bispectrum bin-triplets*gridpts/s at 512^3 (split-MFMA vs FP32); fwd+bwd ms"
+                   if (order == 3 and N == 512 and has_backward)
+                   else f"{names[0]} {names[1]}*gridpts/s at {N}^3 (split-MFMA"
+                        + (", streamed slabs" if streamed else "") + "); "
+                        + ("fwd+bwd ms" if has_backward else "fwd ms")),
         "value": plan.n_closing * G * batch / (ms_step * 1e-3),
         "unit": f"{names[1]}*gridpts/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -252,9 +269,10 @@ def main():
                    "batch": batch, "field": w["field"], "seeds": w["seeds"], "n_closing": plan.n_closing,
                    "precision": args.precision, "parallelism": "none (1 GPU)"},
         "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "plan_s": plan_s,
-        "contract_ms": ctr_ms,
-        "contract_rate": plan.n_closing * G * batch / (ctr_ms * 1e-3),
-        "phase_ms": {k: round(avg(k), 4) for k in ps.PHASES if prof[k][1]},
+        "contract_ms": ctr_ms * launches,
+        "contract_rate": plan.n_closing * G * batch / (ctr_ms * launches * 1e-3),
+        "phase_ms": {k: round(avg(k), 4) for k in ps.PHASES if prof[k][1]},   # per launch
+        "launches_per_step": {k: prof[k][1] // args.steps for k in ps.PHASES if prof[k][1]},
         "roofline": dominant,
         "roofline_other": other,
         "adjoint_weights": n_w,
@@ -267,15 +285,18 @@ def main():
             plan.contract()
         p32 = ps.polyspec_profile_read(plan.handle)
         ms32 = p32["contract"][0] / max(1, p32["contract"][1])
-        out["fp32_contract_ms"] = ms32
-        out["fp32_contract_rate"] = plan.n_closing * G * batch / (ms32 * 1e-3)
+        out["fp32_contract_ms"] = ms32 * launches
+        out["fp32_contract_rate"] = plan.n_closing * G * batch / (ms32 * launches * 1e-3)
         out["split_speedup_vs_fp32"] = ms32 / ctr_ms
         plan.precision = prec
         log(f"fp32 contraction {ms32:.2f} ms vs {args.precision} {ctr_ms:.2f} ms")
     plan.close()
     del x
     torch.cuda.empty_cache()
-    if not args.no_cpu_baseline and order == 3:
+    if streamed:
+        out["config"]["streamed_slab_planes"] = plan.slab_planes
+        out["config"]["input"] = f"half spectrum of {w['spectrum_of']} interpolated to {N}^3"
+    if not args.no_cpu_baseline and order == 3 and not w.get("spectrum_of"):
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(fields[0], w, plan.n_closing * batch, args.cpu_planes)
     print(json.dumps(out), flush=True)

@@ -129,7 +129,29 @@ WORKLOADS = {
                                    field="lognormal", seeds=[2]),
     "pentaspec_256_lognormal": dict(N=256, order=6, n_shells=8, width=1.0, batch=1,
                                     field="lognormal", seeds=[2]),
+    # streamed mode: a 1024^3 input given as its half spectrum, the band-limited
+    # interpolation of the 512^3 field above (zero_padded_half_spectrum)
+    "bispec_1024_streamed": dict(N=1024, order=3, n_shells=64, width=1.0, batch=1,
+                                 field="lognormal", seeds=[5], spectrum_of="bispec_512_lognormal",
+                                 stream=True),
 }
+
+
+def zero_padded_half_spectrum(field: np.ndarray, N_out: int, K: int) -> np.ndarray:
+    """Half spectrum (complex64 [N_out, N_out, N_out/2 + 1]) of the band-limited interpolation
+    of a real N^3 field onto N_out^3, kept on the modes whose components are all at most K
+    in magnitude (K < N/2) and zero elsewhere.
+
+    The unnormalised DFT of the interpolated field is (N_out/N)^3 times that of the field
+    on every mode both grids hold.
+    """
+    N = field.shape[0]
+    hs = np.fft.rfftn(np.asarray(field, dtype=np.float64)) * (N_out / N) ** 3
+    out = np.zeros((N_out, N_out, N_out // 2 + 1), dtype=np.complex64)
+    for src0, dst0 in ((slice(0, K + 1), slice(0, K + 1)), (slice(N - K, N), slice(N_out - K, N_out))):
+        for src1, dst1 in ((slice(0, K + 1), slice(0, K + 1)), (slice(N - K, N), slice(N_out - K, N_out))):
+            out[dst0, dst1, :K + 1] = hs[src0, src1, :K + 1]
+    return out
 
 
 def make_field(kind: str, N: int, seed: int) -> np.ndarray:

@@ -66,7 +66,8 @@ typedef enum {
 enum {
   POLYSPEC_INPUT_HALF_SPECTRUM = 1u, /* polyspec_shells input is delta_hat, complex64 [batch][N][N][N/2+1] */
   POLYSPEC_ALLOW_ALIASING = 2u,      /* accept order*(n_shells+1/2)*width > N: exact mod-N estimator */
-  POLYSPEC_NAN_GUARD = 8u            /* contract reports POLYSPEC_ERR_DEVICE on a non-finite output */
+  POLYSPEC_NAN_GUARD = 8u,           /* contract reports POLYSPEC_ERR_DEVICE on a non-finite output */
+  POLYSPEC_STREAM_SLABS = 16u        /* shell fields are never stored whole: see polyspec_set_slab_planes */
 };
 
 typedef struct {
@@ -125,6 +126,23 @@ polyspec_status polyspec_workspace_size(polyspec_plan_t plan, size_t* bytes);
  * bytes (256-byte aligned).  Must precede the first polyspec_shells call; without
  * it the plan allocates its own on first use and frees it in polyspec_destroy. */
 polyspec_status polyspec_set_workspace(polyspec_plan_t plan, void* d_ptr, size_t bytes);
+
+/* Streamed mode (plans made with POLYSPEC_STREAM_SLABS).  Storing every shell field
+ * takes batch * n_shells * N^3 * 4 bytes (275 GB at N = 1024 with 64 shells), more
+ * than one GPU holds.  A streamed plan keeps only the ball of delta_hat and the first
+ * inverse pass (O(n_shells N^2 K) values); polyspec_contract then runs the last two
+ * inverse passes and the contraction one slab of `planes` x1-planes at a time and adds
+ * each slab's sums in float64, in slab order.  The fields are recomputed by every
+ * polyspec_contract call (and once more by polyspec_shells for their maxima when the
+ * contraction scales its operands: FP16 split, orders 5 and 6).  polyspec_backward and
+ * polyspec_fields are not available on such plans.
+ * polyspec_set_slab_planes sets the slab: a power of two between the smallest slab the
+ * last pass accepts (4 at N = 32, 1 above) and N; it must precede the first use of the
+ * workspace (POLYSPEC_ERR_STATE after it, or on a plan without the flag).  The default
+ * is the largest slab whose fields take at most 2 GiB.  polyspec_slab_planes reports the
+ * slab (N for a plan without the flag). */
+polyspec_status polyspec_set_slab_planes(polyspec_plan_t plan, int32_t planes);
+polyspec_status polyspec_slab_planes(polyspec_plan_t plan, int32_t* planes);
 
 /* Switches the contraction arithmetic (polyspec_precision) for later calls. */
 polyspec_status polyspec_set_precision(polyspec_plan_t plan, int32_t precision);

@@ -20,16 +20,17 @@ import numpy as np
 
 __all__ = [
     "PolyspecError", "Plan", "polyspectrum", "load_library",
-    "FP32", "SPLIT_BF16", "SPLIT_FP16", "INPUT_HALF_SPECTRUM", "ALLOW_ALIASING", "NAN_GUARD",
+    "FP32", "SPLIT_BF16", "SPLIT_FP16", "INPUT_HALF_SPECTRUM", "ALLOW_ALIASING", "NAN_GUARD", "STREAM_SLABS",
     "polyspec_plan", "polyspec_shells", "polyspec_contract", "polyspec_backward",
     "polyspec_workspace_size", "polyspec_set_workspace", "polyspec_set_precision",
+    "polyspec_set_slab_planes", "polyspec_slab_planes",
     "polyspec_tuples", "polyspec_candidates", "polyspec_fields", "polyspec_destroy",
     "polyspec_profile", "polyspec_profile_read", "PHASES",
     "polyspec_status_string", "polyspec_last_error",
 ]
 
 FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2
-INPUT_HALF_SPECTRUM, ALLOW_ALIASING, NAN_GUARD = 1, 2, 8
+INPUT_HALF_SPECTRUM, ALLOW_ALIASING, NAN_GUARD, STREAM_SLABS = 1, 2, 8, 16
 
 STATUS = {0: "POLYSPEC_OK", 1: "POLYSPEC_ERR_INVALID_ARG", 2: "POLYSPEC_ERR_ALIASING",
           3: "POLYSPEC_ERR_OUT_OF_MEMORY", 4: "POLYSPEC_ERR_DEVICE",
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH):
         "polyspec_workspace_size": (ctypes.c_int, [P, D(ctypes.c_size_t)]),
         "polyspec_set_workspace": (ctypes.c_int, [P, V, ctypes.c_size_t]),
         "polyspec_set_precision": (ctypes.c_int, [P, ctypes.c_int32]),
+        "polyspec_set_slab_planes": (ctypes.c_int, [P, ctypes.c_int32]),
+        "polyspec_slab_planes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
         "polyspec_tuples": (ctypes.c_int, [P, D(ctypes.c_int64), V, V]),
         "polyspec_candidates": (ctypes.c_int, [P, D(ctypes.c_int64), V, V]),
         "polyspec_fields": (ctypes.c_int, [P, D(ctypes.c_void_p)]),
@@ -148,6 +151,16 @@ def polyspec_set_precision(plan, precision: int):
     _check(load_library().polyspec_set_precision(plan, precision), "polyspec_set_precision", plan)
 
 
+def polyspec_set_slab_planes(plan, planes: int):
+    _check(load_library().polyspec_set_slab_planes(plan, planes), "polyspec_set_slab_planes", plan)
+
+
+def polyspec_slab_planes(plan) -> int:
+    v = ctypes.c_int32()
+    _check(load_library().polyspec_slab_planes(plan, ctypes.byref(v)), "polyspec_slab_planes", plan)
+    return v.value
+
+
 def polyspec_tuples(plan, order: int):
     lib = load_library()
     n = ctypes.c_int64()
@@ -212,7 +225,7 @@ class Plan:
     """One geometry (grid, order, shells) and batch, bound to torch's current stream."""
 
     def __init__(self, N, order, n_shells, shell_width, batch=1, precision=FP32, box_length=0.0,
-                 flags=0, device=None):
+                 flags=0, device=None, slab_planes=None):
         import torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.N, self.order, self.n_shells, self.width = N, order, n_shells, float(shell_width)
@@ -222,6 +235,9 @@ class Plan:
             self.stream = torch.cuda.current_stream(self.device)
             self.handle = polyspec_plan(N, order, n_shells, shell_width, batch, precision, box_length,
                                         flags, ctypes.c_void_p(self.stream.cuda_stream))
+        if slab_planes is not None:
+            polyspec_set_slab_planes(self.handle, slab_planes)
+        self.slab_planes = polyspec_slab_planes(self.handle)
         self.tuples, self.counts = polyspec_tuples(self.handle, order)
         self.n_closing = len(self.counts)
 

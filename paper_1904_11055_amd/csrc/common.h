@@ -33,6 +33,9 @@ __device__ __forceinline__ cplx<T> cmul_i(cplx<T> a, int s) {
 // component below K_e.  Intermediates between 1-D passes:
 //   H1[z][x1][c][a]   (after the q1 -> x1 transform),  N * B2 * B0 values
 //   H2[z][x0][x1][c]  (after the q0 -> x0 transform),  N * N * B2 values
+// A slab restricts the last two transforms to the planes x1_0 <= x1 < x1_0 + S1 (the
+// whole grid is the slab x1_0 = 0, S1 = N): H2 and the real output then hold S1
+// planes, [z][x0][x1 - x1_0][c] and [z][x0][x1 - x1_0][x2].
 // z enumerates (batch, shell) pairs of one launch: batch = z / spb, shell =
 // shell_base + z % spb (spb = shells per batch; spb = 0 means one unmasked field
 // per batch, batch = z, shell 0).
@@ -44,6 +47,8 @@ struct Geom {
   int spb;
   int shell_base;
   int n_shells;
+  int S1;     // x1 planes of the slab (N for the whole grid)
+  int x1_0;   // first x1 plane of the slab
 };
 
 __device__ __forceinline__ int geom_shell(const Geom& g, int z) {

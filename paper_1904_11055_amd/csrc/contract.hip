@@ -564,9 +564,10 @@ __global__ __launch_bounds__(kJThreads, 1) void contract_j3(CtrJParams p) {
 }
 
 // Sum float32 partials over chunk ranges in float64, fixed order.
-// level 1: tmp[b][grp][e] = sum_{c in grp} part[b][c][e]
+// level 1: tmp[b][grp][e] = sum_{c in grp} part[b][c][e], or += when accumulating
+// over the slabs of a streamed contraction
 __global__ void reduce_chunks_f32(const float* __restrict__ part, double* __restrict__ tmp, int n_chunks,
-                                  int chunks_per_group, int n_groups, long long n_ent) {
+                                  int chunks_per_group, int n_groups, long long n_ent, int accumulate) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int grp = blockIdx.y;
   const int b = blockIdx.z;
@@ -576,7 +577,8 @@ __global__ void reduce_chunks_f32(const float* __restrict__ part, double* __rest
   const float* src = part + (size_t)b * n_chunks * n_ent;
   double s = 0.0;
   for (int c = c0; c < c1; ++c) s += (double)src[(size_t)c * n_ent + e];
-  tmp[((size_t)b * n_groups + grp) * n_ent + e] = s;
+  double& dst = tmp[((size_t)b * n_groups + grp) * n_ent + e];
+  dst = accumulate ? dst + s : s;
 }
 
 __global__ void reduce_chunks_f64(const double* __restrict__ part, double* __restrict__ tmp, int n_chunks,
@@ -1202,9 +1204,10 @@ hipError_t launch_contract_j3(int prec, const CtrJParams& p, int batch, hipStrea
 }
 
 hipError_t launch_reduce_f32(const float* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
-                             int batch, hipStream_t st) {
+                             bool accumulate, int batch, hipStream_t st) {
   dim3 grid((unsigned)((n_ent + 255) / 256), n_groups, batch);
-  hipLaunchKernelGGL(reduce_chunks_f32, grid, dim3(256), 0, st, part, tmp, n_chunks, cpg, n_groups, n_ent);
+  hipLaunchKernelGGL(reduce_chunks_f32, grid, dim3(256), 0, st, part, tmp, n_chunks, cpg, n_groups, n_ent,
+                     accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restr
   }
 }
 
-// P2: pencils (x1, c), transform q0 -> x0.  grid (ceil(B2/P), N, nz)
+// P2: pencils (x1, c), transform q0 -> x0, for the x1 planes of the slab.
+// grid (ceil(B2/P), S1, nz)
 template <typename T, int N>
 __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict__ H1,
                                                       const int* __restrict__ qmax,
@@ -129,7 +130,8 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
   const int z = blockIdx.z;
   const int s = geom_shell(g, z);
   const int c0 = blockIdx.x * P;
-  const int x1 = blockIdx.y;
+  const int xs = blockIdx.y;          // plane within the slab
+  const int x1 = g.x1_0 + xs;
   const int Kc = g.Kc;
   const int qm = qmax[s];
   if (c0 * c0 > qm) return;  // every column of this chunk lies outside the shell
@@ -148,13 +150,13 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
   }
   __syncthreads();
   fft_block<T, N, P, NS, +1>(buf, stw);
-  cplx<T>* out = H2 + (size_t)z * N * N * g.B2;
+  cplx<T>* out = H2 + (size_t)z * N * g.S1 * g.B2;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x0 = u / P;
     const int c = c0 + pp;
-    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * N + x1) * g.B2 + c] = buf[pp * NS + pad8(x0)];
+    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * g.S1 + xs) * g.B2 + c] = buf[pp * NS + pad8(x0)];
   }
 }
 
@@ -185,10 +187,10 @@ __device__ __forceinline__ int col_max(const Geom& g, int qm) {
   return cm;
 }
 
-// P3 (full grid): rows (x0, x1) in pairs, complex-to-real over x2.
-// out[z * G + row * N + x2]; optional |value| maximum per z (as float bits).
+// P3: rows (x0, x1) of the slab in pairs, complex-to-real over x2.
+// out[z * N S1 N + row * N + x2]; optional |value| maximum per z (as float bits).
 // Dynamic LDS: the 2P input rows, 2P (Kc + 1) complex values.
-// grid (N*N/2/P, 1, nz)
+// grid (N*S1/2/P, 1, nz)
 template <int N>
 __global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restrict__ H2,
                                                       const int* __restrict__ qmax,
@@ -205,9 +207,10 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restr
   const int z = blockIdx.z;
   const int cm = col_max(g, qmax[geom_shell(g, z)]);
   const int W = cm + 1;
-  const size_t G = (size_t)N * N * N;
+  const size_t rows = (size_t)N * g.S1;   // rows (x0, x1) of the slab
+  const size_t G = rows * N;
   const int row0 = blockIdx.x * 2 * P;  // first of the block's 2P rows
-  const cplx<T>* in = H2 + (size_t)z * N * N * g.B2 + (size_t)row0 * g.B2;
+  const cplx<T>* in = H2 + (size_t)z * rows * g.B2 + (size_t)row0 * g.B2;
   for (int u = threadIdx.x; u < 2 * P * W; u += kFftThreads) {
     const int r = u / W, c = u - r * W;
     raw[u] = in[(size_t)r * g.B2 + c];
@@ -495,7 +498,8 @@ template <typename T>
 hipError_t launch_c2r_p2(const cplx<T>* H1, const int* qmax, cplx<T>* H2, const cplx<T>* tw, Geom g, int nz,
                          hipStream_t st) {
   const int P = FftCfg<T>::kColElems / g.N;
-  dim3 grid((g.B2 + P - 1) / P, g.N, nz);
+  if (g.S1 < 1 || g.x1_0 < 0 || g.x1_0 + g.S1 > g.N) return hipErrorInvalidValue;
+  dim3 grid((g.B2 + P - 1) / P, g.S1, nz);
   switch (g.N) {
 #define CASE(n) case n: hipLaunchKernelGGL((c2r_p2<T, n>), grid, dim3(kFftThreads), 0, st, H1, qmax, H2, tw, g); break;
     PS_FOR_EACH_N(CASE)
@@ -508,7 +512,9 @@ hipError_t launch_c2r_p2(const cplx<T>* H1, const int* qmax, cplx<T>* H2, const 
 hipError_t launch_c2r_p3(const cplx<float>* H2, const int* qmax, float* out, unsigned* absmax,
                          const cplx<float>* tw, Geom g, int nz, hipStream_t st) {
   const int P = FftCfg<float>::kRowElems / g.N;
-  dim3 grid(g.N * g.N / 2 / P, 1, nz);
+  if (g.S1 < 1 || g.x1_0 < 0 || g.x1_0 + g.S1 > g.N || ((size_t)g.N * g.S1) % (2 * P) != 0)
+    return hipErrorInvalidValue;
+  dim3 grid((unsigned)((size_t)g.N * g.S1 / 2 / P), 1, nz);
   const size_t shm = (size_t)2 * P * g.B2 * sizeof(cplx<float>);
   switch (g.N) {
 #define CASE(n) \

@@ -74,6 +74,10 @@ struct polyspec_plan_s {
   int Kc = 0, B0 = 0, B2 = 0, n_blk = 0;
   long long G = 0;
   bool alias_free = true;
+  // streamed mode: the last two inverse passes and the contraction run one slab of
+  // S1 x1-planes at a time, so only a slab of every shell field is ever stored
+  bool streamed = false;
+  int S1 = 0, n_slabs = 1;
 
   std::vector<int64_t> thr;        // T_1..T_{nb+1}
   std::vector<int16_t> shell_of_q;
@@ -220,7 +224,37 @@ Geom make_geom(const polyspec_plan_s* p, int spb, int shell_base) {
   g.spb = spb;
   g.shell_base = shell_base;
   g.n_shells = p->nb;
+  g.S1 = p->N;
+  g.x1_0 = 0;
   return g;
+}
+
+// Grid points of one contraction launch: the whole grid, or one slab.
+long long launch_points(const polyspec_plan_s* p) { return p->streamed ? (long long)p->N * p->N * p->S1 : p->G; }
+
+// Chunking of one contraction launch into workgroups of ksteps 64-point stages.
+void set_chunking(polyspec_plan_s* p) {
+  const long long steps = launch_points(p) / ps::kStagePtsHost;
+  long long ks = steps / 512;
+  ks = std::max(1LL, std::min(256LL, ks));
+  while (steps % ks) --ks;
+  p->ksteps = (int)ks;
+  p->n_chunks = (int)(steps / ks);
+  // the shell-block aligned kernel works on whole 256-point stages
+  long long ksj = std::max(4LL, ks);
+  while (steps % ksj) ++ksj;
+  p->ksteps_j = (int)ksj;
+  p->n_chunks_j = (int)(steps / ksj);
+  p->red_cpg = 64;
+  p->red_groups = (p->n_chunks + p->red_cpg - 1) / p->red_cpg;
+}
+
+// Smallest slab the last pass accepts: N S1 rows must split into pairs of P-row blocks.
+int min_slab_planes(int N) {
+  const int P = 2048 / N;
+  int s1 = 1;
+  while (((long long)N * s1) % (2 * P) != 0) s1 *= 2;
+  return s1;
 }
 
 template <typename T>
@@ -251,17 +285,20 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   const size_t zf = (size_t)p->batch * p->nb;
   L.box = align256((size_t)p->batch * box_elems * sizeof(cplx<float>));
-  const bool adjoint = p->order == 3 || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
+  const bool adjoint = !p->streamed && (p->order == 3 || (p->order == 4 && p->nb <= ps::kAdj4MaxShells));
+  const size_t planes = p->streamed ? p->S1 : p->N;   // x1 planes held of H2 and of the fields
   L.gbox = adjoint ? L.box : 0;
   L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
-  L.H2 = align256(zf * p->N * p->N * p->B2 * sizeof(cplx<float>));
-  L.D = align256(zf * (size_t)p->G * sizeof(float));
+  // H2 also takes the input's first transform, batch x N^2 x B2, when a slab is smaller
+  L.H2 = align256(std::max(zf * p->N * planes, (size_t)p->batch * p->N * p->N) * p->B2 * sizeof(cplx<float>));
+  L.D = align256(zf * (size_t)p->N * planes * p->N * sizeof(float));
   L.A = (adjoint && !ps::adjoint_fuses_rows(p->N)) ? L.D : 0;   // adjoint fields only when not fused
   const size_t tiles = (size_t)std::max(p->n_tiles, p->n_tiles_j);
   L.partials = align256((size_t)p->batch * p->n_chunks * tiles * 256 * sizeof(float));
   L.red = align256((size_t)p->batch * p->red_groups * tiles * 256 * sizeof(double));
   L.absmax = align256(zf * sizeof(unsigned)) + align256(zf * ps::kAbsmaxSpreadHost * sizeof(unsigned));
-  L.W = p->order == 3 ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16)
+  L.W = !adjoint ? 0
+        : p->order == 3 ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16)
         : adjoint ? align256((size_t)p->batch * (p->nb * (p->nb + 1) / 2) * ps::kAdj4WordsPerItem * 16)
                   : 0;
   L.total = L.box + L.gbox + L.H1 + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
@@ -682,7 +719,8 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   if (d.precision < 0 || d.precision > 2) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown precision");
   if (!(d.box_length >= 0.0) || !std::isfinite(d.box_length))
     return p->fail(POLYSPEC_ERR_INVALID_ARG, "box_length must be finite and >= 0");
-  const uint32_t known = POLYSPEC_INPUT_HALF_SPECTRUM | POLYSPEC_ALLOW_ALIASING | POLYSPEC_NAN_GUARD;
+  const uint32_t known =
+      POLYSPEC_INPUT_HALF_SPECTRUM | POLYSPEC_ALLOW_ALIASING | POLYSPEC_NAN_GUARD | POLYSPEC_STREAM_SLABS;
   if (d.flags & ~known) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown flag bits");
   Dyadic w;
   if (!to_dyadic(d.shell_width, &w)) return p->fail(POLYSPEC_ERR_INVALID_ARG, "shell_width must be finite and > 0");
@@ -739,20 +777,17 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   std::vector<int> ent_j_of_cand;
   PS_TRY(build_jsched(p, &ent_j_of_cand));
 
-  // chunking of the grid for the contraction
-  const long long steps = p->G / ps::kStagePtsHost;
-  long long ks = steps / 512;
-  ks = std::max(1LL, std::min(256LL, ks));
-  while (steps % ks) --ks;
-  p->ksteps = (int)ks;
-  p->n_chunks = (int)(steps / ks);
-  // the shell-block aligned kernel works on whole 256-point stages
-  long long ksj = std::max(4LL, ks);
-  while (steps % ksj) ++ksj;
-  p->ksteps_j = (int)ksj;
-  p->n_chunks_j = (int)(steps / ksj);
-  p->red_cpg = 64;
-  p->red_groups = (p->n_chunks + p->red_cpg - 1) / p->red_cpg;
+  // streamed mode: the largest power-of-two slab whose shell fields take at most
+  // 2 GiB (polyspec_set_slab_planes overrides it before the first use)
+  p->streamed = (d.flags & POLYSPEC_STREAM_SLABS) != 0;
+  if (p->streamed) {
+    int s1 = p->N;
+    while (s1 > min_slab_planes(p->N) && (size_t)p->batch * p->nb * s1 * (size_t)p->N * p->N * 4 > ((size_t)2 << 30))
+      s1 /= 2;
+    p->S1 = s1;
+    p->n_slabs = p->N / s1;
+  }
+  set_chunking(p);
 
   PS_TRY(upload(p, &p->tw32, twiddles<float>(p->N)));
   PS_TRY(upload(p, &p->shell_q, p->shell_of_q));
@@ -927,9 +962,61 @@ polyspec_status polyspec_set_precision(polyspec_plan_t p, int32_t precision) {
   return POLYSPEC_OK;
 }
 
+polyspec_status polyspec_set_slab_planes(polyspec_plan_t p, int32_t planes) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!p->streamed) return p->fail(POLYSPEC_ERR_STATE, "slab planes apply to plans made with POLYSPEC_STREAM_SLABS");
+  if (p->ws) return p->fail(POLYSPEC_ERR_STATE, "the workspace is already sized");
+  if (planes < min_slab_planes(p->N) || planes > p->N || (planes & (planes - 1)) != 0)
+    return p->fail(POLYSPEC_ERR_INVALID_ARG, "planes must be a power of two between " +
+                                                 std::to_string(min_slab_planes(p->N)) + " and N");
+  p->S1 = planes;
+  p->n_slabs = p->N / planes;
+  set_chunking(p);
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_slab_planes(polyspec_plan_t p, int32_t* planes) {
+  if (!p || !planes) return POLYSPEC_ERR_INVALID_ARG;
+  *planes = p->streamed ? p->S1 : p->N;
+  return POLYSPEC_OK;
+}
+
 // The contraction scales every shell field by a power of two (from its largest
 // magnitude) for the FP16 split, and at orders 5 and 6 for every precision.
 static bool scaled_contraction(const polyspec_plan_s* p) { return p->prec == POLYSPEC_SPLIT_FP16 || p->order >= 5; }
+
+// Last two inverse passes for the x1-planes [x1_0, x1_0 + S1) of every shell (the whole
+// grid when not streamed), optionally with the per-field maxima.
+static polyspec_status shell_slab(polyspec_plan_t p, int slab, unsigned* absmax_part) {
+  Geom gs = make_geom(p, p->nb, 1);
+  if (p->streamed) {
+    gs.S1 = p->S1;
+    gs.x1_0 = slab * p->S1;
+  }
+  const int nz = p->batch * p->nb;
+  hipStream_t st = p->stream;
+  PS_TIMED(p, POLYSPEC_PH_SHELL_P2, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, (const cplx<float>*)p->tw32.p, gs, nz,
+                                     st));
+  PS_TIMED(p, POLYSPEC_PH_SHELL_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D, absmax_part,
+                                                      (const cplx<float>*)p->tw32.p, gs, nz, st));
+  return POLYSPEC_OK;
+}
+
+// Per-field maxima of the shell fields (the scaling of the contraction's operands):
+// resident fields are scanned; streamed ones are computed slab by slab and dropped.
+static polyspec_status field_maxima(polyspec_plan_t p) {
+  const int nz = p->batch * p->nb;
+  hipStream_t st = p->stream;
+  PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
+  if (p->streamed) {
+    for (int k = 0; k < p->n_slabs; ++k) PS_TRY(shell_slab(p, k, p->absmax_part));
+  } else {
+    PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));
+  }
+  PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
+  p->absmax_valid = true;
+  return POLYSPEC_OK;
+}
 
 polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
@@ -941,34 +1028,102 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM) {
     PS_HIP(p, ps::launch_box_from_half_spectrum((const cplx<float>*)d_delta, p->box, gin, p->batch, st));
   } else {
+    // the input transform uses H2 and H1 as scratch (sized for it in streamed plans too)
     PS_TIMED(p, POLYSPEC_PH_INPUT_Q3, ps::launch_r2c_q3((const float*)d_delta, p->H2, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
     PS_TIMED(p, POLYSPEC_PH_INPUT_Q2, ps::launch_r2c_q2(p->H2, p->H1, (const cplx<float>*)p->tw32.p, gin, p->batch, st));
     PS_TIMED(p, POLYSPEC_PH_INPUT_Q1, ps::launch_r2c_q1<false>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->box,
                                        (const cplx<float>*)p->tw32.p, gin, p->batch, st));
   }
   Geom gs = make_geom(p, p->nb, 1);
-  const bool want_max = scaled_contraction(p);
-  if (want_max) PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
   PS_TIMED(p, POLYSPEC_PH_SHELL_P1, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
                                             (const cplx<float>*)p->tw32.p, gs, nz, st));
-  PS_TIMED(p, POLYSPEC_PH_SHELL_P2, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, (const cplx<float>*)p->tw32.p, gs, nz,
-                                     st));
-  PS_TIMED(p, POLYSPEC_PH_SHELL_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, p->D,
-                                                      want_max ? p->absmax_part : nullptr,
-                                                      (const cplx<float>*)p->tw32.p, gs, nz, st));
-  if (want_max) PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
-  p->absmax_valid = want_max;
+  p->absmax_valid = false;
+  if (p->streamed) {
+    // the fields are made slab by slab inside polyspec_contract; only their maxima
+    // are needed now, and only when the contraction scales its operands
+    if (scaled_contraction(p)) PS_TRY(field_maxima(p));
+  } else {
+    const bool want_max = scaled_contraction(p);
+    if (want_max) PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
+    PS_TRY(shell_slab(p, 0, want_max ? p->absmax_part : nullptr));
+    if (want_max) PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
+    p->absmax_valid = want_max;
+  }
   p->have_fields = true;
   return POLYSPEC_OK;
 }
 
-// FP64 reduction of the contraction's partial tiles, then normalisation and gather.
-static polyspec_status finish_contract(polyspec_plan_t p, long long n_ent, int n_chunks, const int* ent,
-                                       double* d_out, double* d_raw_sums) {
+// One contraction launch over the fields in D (the whole grid or one slab) and its
+// FP64 reduction over chunks into p->red, added to what is there when `accumulate`.
+// Returns the tile entries and entry table that the gather needs.
+static polyspec_status contract_launch(polyspec_plan_t p, bool accumulate, long long* n_ent, int* groups,
+                                       const int** ent) {
   hipStream_t st = p->stream;
+  int n_chunks;
+  if (p->jsched && p->prec == POLYSPEC_SPLIT_FP16 && p->ksteps_j % 4 == 0) {   // whole 256-point stages
+    ps::CtrJParams jp;
+    jp.D = p->D;
+    jp.absmax = p->absmax;
+    jp.tile_of_slot = (const int*)p->jtile_d.p;
+    jp.slot_mask = (const unsigned*)p->jmask_d.p;
+    jp.partials = p->partials;
+    jp.G = launch_points(p);
+    jp.n_shells = p->nb;
+    jp.n_blk = p->n_blk;
+    jp.n_tiles = p->n_tiles_j;
+    jp.ksteps = p->ksteps_j;
+    jp.n_chunks = p->n_chunks_j;
+    PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract_j3(p->prec, jp, p->batch, st));
+    *n_ent = (long long)p->n_tiles_j * 256;
+    n_chunks = p->n_chunks_j;
+    *ent = (const int*)p->ent_j_d.p;
+  } else {
+    ps::CtrParams cp;
+    cp.D = p->D;
+    cp.pair_uv = (const int*)p->pairs_d.p;
+    cp.slot_uni = (const int*)p->slots_d.p;
+    cp.slot_lane = (const int*)p->slot_lane_d.p;
+    cp.slot_tile = (const int*)p->slot_tile_d.p;
+    cp.absmax = p->absmax;
+    cp.partials = p->partials;
+    cp.G = launch_points(p);
+    cp.n_shells = p->nb;
+    cp.n_blk = p->n_blk;
+    cp.n_pairs_padded = p->n_pairs_padded;
+    cp.n_tiles = p->n_tiles;
+    cp.ksteps = p->ksteps;
+    cp.n_chunks = p->n_chunks;
+    PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
+    *n_ent = (long long)p->n_tiles * 256;
+    n_chunks = p->n_chunks;
+    *ent = (const int*)p->ent_d.p;
+  }
   // chunk groups of red_cpg chunks; the aligned kernel has at most as many chunks
-  const int groups = (n_chunks + p->red_cpg - 1) / p->red_cpg;
-  PS_TIMED(p, POLYSPEC_PH_REDUCE, ps::launch_reduce_f32(p->partials, p->red, n_chunks, p->red_cpg, groups, n_ent, p->batch, st));
+  *groups = (n_chunks + p->red_cpg - 1) / p->red_cpg;
+  PS_TIMED(p, POLYSPEC_PH_REDUCE, ps::launch_reduce_f32(p->partials, p->red, n_chunks, p->red_cpg, *groups, *n_ent,
+                                                        accumulate, p->batch, st));
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_raw_sums) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
+  if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_contract before polyspec_shells");
+  hipStream_t st = p->stream;
+  if (scaled_contraction(p) && !p->absmax_valid) PS_TRY(field_maxima(p));  // precision switched after shells
+  long long n_ent = 0;
+  int groups = 0;
+  const int* ent = nullptr;
+  if (p->streamed) {
+    // slab by slab: the slab's fields, its contraction, and its sums added in FP64 in
+    // slab order (a fixed order, so reruns are bitwise equal)
+    for (int k = 0; k < p->n_slabs; ++k) {
+      PS_TRY(shell_slab(p, k, nullptr));
+      PS_TRY(contract_launch(p, k > 0, &n_ent, &groups, &ent));
+    }
+  } else {
+    PS_TRY(contract_launch(p, false, &n_ent, &groups, &ent));
+  }
   const bool guard = p->desc.flags & POLYSPEC_NAN_GUARD;
   if (guard) PS_HIP(p, ps::launch_fill_u32(p->flag_d.p, 0u, 1, st));
   const int ncl = (int)p->closing.size();
@@ -985,56 +1140,10 @@ static polyspec_status finish_contract(polyspec_plan_t p, long long n_ent, int n
   return POLYSPEC_OK;
 }
 
-polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_raw_sums) {
-  if (!p) return POLYSPEC_ERR_INVALID_ARG;
-  if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
-  if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_contract before polyspec_shells");
-  hipStream_t st = p->stream;
-  if (scaled_contraction(p) && !p->absmax_valid) {  // precision switched after polyspec_shells
-    const int nz = p->batch * p->nb;
-    PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
-    PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));
-    PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
-    p->absmax_valid = true;
-  }
-  if (p->jsched && p->prec == POLYSPEC_SPLIT_FP16 && p->ksteps_j % 4 == 0) {   // whole 256-point stages
-    ps::CtrJParams jp;
-    jp.D = p->D;
-    jp.absmax = p->absmax;
-    jp.tile_of_slot = (const int*)p->jtile_d.p;
-    jp.slot_mask = (const unsigned*)p->jmask_d.p;
-    jp.partials = p->partials;
-    jp.G = p->G;
-    jp.n_shells = p->nb;
-    jp.n_blk = p->n_blk;
-    jp.n_tiles = p->n_tiles_j;
-    jp.ksteps = p->ksteps_j;
-    jp.n_chunks = p->n_chunks_j;
-    PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract_j3(p->prec, jp, p->batch, st));
-    return finish_contract(p, (long long)p->n_tiles_j * 256, p->n_chunks_j, (const int*)p->ent_j_d.p, d_out,
-                           d_raw_sums);
-  }
-  ps::CtrParams cp;
-  cp.D = p->D;
-  cp.pair_uv = (const int*)p->pairs_d.p;
-  cp.slot_uni = (const int*)p->slots_d.p;
-  cp.slot_lane = (const int*)p->slot_lane_d.p;
-  cp.slot_tile = (const int*)p->slot_tile_d.p;
-  cp.absmax = p->absmax;
-  cp.partials = p->partials;
-  cp.G = p->G;
-  cp.n_shells = p->nb;
-  cp.n_blk = p->n_blk;
-  cp.n_pairs_padded = p->n_pairs_padded;
-  cp.n_tiles = p->n_tiles;
-  cp.ksteps = p->ksteps;
-  cp.n_chunks = p->n_chunks;
-  PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
-  return finish_contract(p, (long long)p->n_tiles * 256, p->n_chunks, (const int*)p->ent_d.p, d_out, d_raw_sums);
-}
-
 polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, float* d_grad_delta) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (p->streamed)
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward needs resident shell fields (a plan without POLYSPEC_STREAM_SLABS)");
   if (p->order != 3 && !(p->order == 4 && p->nb <= ps::kAdj4MaxShells))
     return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward is implemented for order 3, and order 4 with at most 32 shells");
   if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM)
@@ -1098,6 +1207,7 @@ polyspec_status polyspec_candidates(polyspec_plan_t p, int64_t* n_candidates, in
 polyspec_status polyspec_fields(polyspec_plan_t p, const float** d_fields) {
   if (!p || !d_fields) return POLYSPEC_ERR_INVALID_ARG;
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "no shell fields yet");
+  if (p->streamed) return p->fail(POLYSPEC_ERR_STATE, "a streamed plan keeps no whole shell fields");
   *d_fields = p->D;
   return POLYSPEC_OK;
 }

@@ -162,6 +162,79 @@ def test_unit_spectrum_gives_one_high_orders(gpu, order, nb):
     plan.close()
 
 
+# Streamed plans: the last two inverse passes and the contraction run one x1-slab at
+# a time (8 slabs of 8 planes at 64^3, 8 slabs of the smallest 4-plane slab at 32^3).
+@pytest.mark.parametrize("order,nb,precision,tol", [(3, 16, 0, 1e-5), (3, 16, 1, 1e-4), (3, 16, 2, 1e-4),
+                                                    (4, 9, 2, 1e-4), (2, 20, 0, 1e-5)])
+def test_streamed_matches_oracle_and_resident(gpu, bispec64, order, nb, precision, tol):
+    import torch
+    ps = _ps()
+    delta = bispec64[0] if order == 3 else fieldgen.lognormal_field(64, 40 + order).astype(np.float32)
+    ref = bispec64[1] if order == 3 else O.polyspectrum(delta.astype(np.float64), order, nb, 1.0)
+    plan = ps.Plan(64, order, nb, 1.0, precision=precision, flags=ps.STREAM_SLABS, slab_planes=8,
+                   device="cuda:0")
+    assert plan.slab_planes == 8
+    x = torch.from_numpy(delta[None]).to("cuda:0")
+    plan.shells(x)
+    B1 = plan.contract().cpu().numpy()
+    B2 = plan.contract().cpu().numpy()
+    assert np.array_equal(B1, B2)                       # fixed slab order: bitwise reruns
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(B1[0], ref["B"]) < tol
+    _, Bres, _ = _run(delta, order, nb, 1.0, precision=precision)
+    assert _rel(B1[0], Bres[0]) < tol
+    plan.close()
+
+
+@pytest.mark.parametrize("order,precision,tol", [(3, 2, 1e-4), (5, 0, 1e-5 * 5 / 3)])
+def test_streamed_batch_and_smallest_slab(gpu, order, precision, tol):
+    import torch
+    ps = _ps()
+    nb = 10 if order == 3 else 4
+    fields = np.stack([fieldgen.lognormal_field(32, s).astype(np.float32) for s in (50, 51)])
+    plan = ps.Plan(32, order, nb, 1.0, batch=2, precision=precision, flags=ps.STREAM_SLABS, slab_planes=4,
+                   device="cuda:0")
+    plan.shells(torch.from_numpy(fields).to("cuda:0"))
+    B, S = (a.cpu().numpy() for a in plan.contract(raw=True))
+    for b in range(2):
+        ref = O.polyspectrum(fields[b].astype(np.float64), order, nb, 1.0)
+        assert np.array_equal(plan.counts, ref["counts"])
+        assert _rel(S[b], ref["sums"]) < tol
+    plan.close()
+
+
+def test_streamed_plan_limits(gpu):
+    import torch
+    ps = _ps()
+    plan = ps.Plan(32, 3, 6, 1.0, flags=ps.STREAM_SLABS, device="cuda:0")
+    assert plan.slab_planes == 32                          # 6 shells at 32^3 fit one 2 GiB slab
+    with pytest.raises(ps.PolyspecError) as e:
+        ps.polyspec_set_slab_planes(plan.handle, 2)       # below the smallest slab at N = 32
+    assert e.value.status == 1
+    with pytest.raises(ps.PolyspecError) as e:
+        ps.polyspec_set_slab_planes(plan.handle, 12)      # not a power of two
+    assert e.value.status == 1
+    ps.polyspec_set_slab_planes(plan.handle, 16)
+    assert ps.polyspec_slab_planes(plan.handle) == 16
+    plan.shells(torch.from_numpy(fieldgen.gaussian_field(32, 3).astype(np.float32)[None]).to("cuda:0"))
+    with pytest.raises(ps.PolyspecError) as e:
+        ps.polyspec_set_slab_planes(plan.handle, 8)       # workspace already sized
+    assert e.value.status == 6
+    with pytest.raises(ps.PolyspecError) as e:
+        plan.backward(torch.ones((1, plan.n_closing), dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == 7
+    with pytest.raises(ps.PolyspecError) as e:
+        plan.fields()
+    assert e.value.status == 6
+    plan.close()
+    resident = ps.Plan(32, 3, 6, 1.0, device="cuda:0")
+    assert resident.slab_planes == 32
+    with pytest.raises(ps.PolyspecError) as e:
+        ps.polyspec_set_slab_planes(resident.handle, 8)
+    assert e.value.status == 6
+    resident.close()
+
+
 @pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
 def test_aliased_configuration(gpu, precision, tol):
     ps = _ps()
