@@ -133,9 +133,10 @@ polyspec_status polyspec_set_workspace(polyspec_plan_t plan, void* d_ptr, size_t
  * inverse pass (O(n_shells N^2 K) values); polyspec_contract then runs the last two
  * inverse passes and the contraction one slab of `planes` x1-planes at a time and adds
  * each slab's sums in float64, in slab order.  The fields are recomputed by every
- * polyspec_contract call (and once more by polyspec_shells for their maxima when the
- * contraction scales its operands: FP16 split, orders 5 and 6).  polyspec_backward and
- * polyspec_fields are not available on such plans.
+ * polyspec_contract call; when the contraction scales its operands (FP16 split, orders
+ * 5 and 6) each slab takes its own per-field maxima, and the float64 reduction of the
+ * slab removes the scale.  polyspec_backward and polyspec_fields are not available on
+ * such plans.
  * polyspec_set_slab_planes sets the slab: a power of two between the smallest slab the
  * last pass accepts (4 at N = 32, 1 above) and N; it must precede the first use of the
  * workspace (POLYSPEC_ERR_STATE after it, or on a plan without the flag).  The default

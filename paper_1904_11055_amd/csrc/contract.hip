@@ -563,11 +563,27 @@ __global__ __launch_bounds__(kJThreads, 1) void contract_j3(CtrJParams p) {
   }
 }
 
+// Power of two that undoes the operand scaling of the contraction for closing tuple t
+// of field b: the shells' scales, and for FP16 at orders 5 and 6 the extra 2^-7 of
+// every triple operand.
+__device__ __forceinline__ int tuple_unscale_exp(const unsigned* absmax, int b, int n_shells, const int* bins,
+                                                 int t, int order, int prec) {
+  int ex = 0;
+  for (int j = 0; j < order; ++j) ex += shell_scale_exp(absmax, b * n_shells + bins[t * order + j]);
+  const int triples = prec != kFP16 ? 0 : order == 5 ? 1 : order == 6 ? 2 : 0;
+  return triples * kTripleShift - ex;
+}
+
 // Sum float32 partials over chunk ranges in float64, fixed order.
 // level 1: tmp[b][grp][e] = sum_{c in grp} part[b][c][e], or += when accumulating
-// over the slabs of a streamed contraction
+// over the slabs of a streamed contraction.  With `closing_of_entry` (streamed plans
+// whose operands were scaled by the slab's own maxima) the sum of an entry is unscaled
+// here, with the exponents of the closing tuple it holds; entries holding no closing
+// tuple are left at zero.
 __global__ void reduce_chunks_f32(const float* __restrict__ part, double* __restrict__ tmp, int n_chunks,
-                                  int chunks_per_group, int n_groups, long long n_ent, int accumulate) {
+                                  int chunks_per_group, int n_groups, long long n_ent, int accumulate,
+                                  const int* __restrict__ closing_of_entry, const int* __restrict__ bins, int order,
+                                  const unsigned* __restrict__ absmax, int n_shells, int prec) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int grp = blockIdx.y;
   const int b = blockIdx.z;
@@ -577,6 +593,10 @@ __global__ void reduce_chunks_f32(const float* __restrict__ part, double* __rest
   const float* src = part + (size_t)b * n_chunks * n_ent;
   double s = 0.0;
   for (int c = c0; c < c1; ++c) s += (double)src[(size_t)c * n_ent + e];
+  if (closing_of_entry != nullptr) {
+    const int t = closing_of_entry[e];
+    s = t < 0 ? 0.0 : ldexp(s, tuple_unscale_exp(absmax, b, n_shells, bins, t, order, prec));
+  }
   double& dst = tmp[((size_t)b * n_groups + grp) * n_ent + e];
   dst = accumulate ? dst + s : s;
 }
@@ -609,12 +629,10 @@ __global__ void gather_normalize(const double* __restrict__ tmp, int n_groups, l
   const double* src = tmp + (size_t)b * n_groups * n_ent;
   double s = 0.0;
   for (int grp = 0; grp < n_groups; ++grp) s += src[(size_t)grp * n_ent + e];
-  if (prec == kFP16 || order >= 5) {   // the scaling of the contraction's operands
-    int ex = 0;
-    for (int j = 0; j < order; ++j) ex += shell_scale_exp(absmax, b * n_shells + bins[t * order + j]);
-    const int triples = prec != kFP16 ? 0 : order == 5 ? 1 : order == 6 ? 2 : 0;   // FP16 triple operands
-    s = ldexp(s, triples * kTripleShift - ex);
-  }
+  // the scaling of the contraction's operands (absmax is null when the reduction has
+  // already removed it)
+  if (absmax != nullptr && (prec == kFP16 || order >= 5))
+    s = ldexp(s, tuple_unscale_exp(absmax, b, n_shells, bins, t, order, prec));
   const double B = s * fnorm[t];
   out[(size_t)b * n_closing + t] = B;
   if (raw != nullptr) raw[(size_t)b * n_closing + t] = s;
@@ -1204,10 +1222,11 @@ hipError_t launch_contract_j3(int prec, const CtrJParams& p, int batch, hipStrea
 }
 
 hipError_t launch_reduce_f32(const float* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
-                             bool accumulate, int batch, hipStream_t st) {
+                             bool accumulate, const int* closing_of_entry, const int* bins, int order,
+                             const unsigned* absmax, int n_shells, int prec, int batch, hipStream_t st) {
   dim3 grid((unsigned)((n_ent + 255) / 256), n_groups, batch);
   hipLaunchKernelGGL(reduce_chunks_f32, grid, dim3(256), 0, st, part, tmp, n_chunks, cpg, n_groups, n_ent,
-                     accumulate ? 1 : 0);
+                     accumulate ? 1 : 0, closing_of_entry, bins, order, absmax, n_shells, prec);
   return hipGetLastError();
 }
 

@@ -90,7 +90,8 @@ struct CtrJParams {
 };
 hipError_t launch_contract_j3(int prec, const CtrJParams& p, int batch, hipStream_t st);
 hipError_t launch_reduce_f32(const float* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
-                             bool accumulate, int batch, hipStream_t st);
+                             bool accumulate, const int* closing_of_entry, const int* bins, int order,
+                             const unsigned* absmax, int n_shells, int prec, int batch, hipStream_t st);
 hipError_t launch_reduce_f64(const double* part, double* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
                              int batch, hipStream_t st);
 hipError_t launch_gather(const double* tmp, int n_groups, long long n_ent, const int* ent_idx, const int* bins,

@@ -104,6 +104,7 @@ struct polyspec_plan_s {
   // device tables
   DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_lane_d, slot_tile_d, ent_d, bins_d, fnorm_d, lookup_d, wmask_d, flag_d;
   DevBuf jtile_d, jmask_d, ent_j_d;
+  DevBuf closing_of_ent_d, closing_of_ent_j_d;   // streamed plans: tile entry -> closing tuple (or -1)
   // workspace carving
   DevBuf own_ws;
   char* ws = nullptr;
@@ -827,6 +828,17 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   }
   PS_TRY(upload(p, &p->ent_d, ent));
   if (p->jsched) PS_TRY(upload(p, &p->ent_j_d, ent_j));
+  if (p->streamed) {
+    // the reduction of a streamed slab unscales each entry with its tuple's exponents
+    std::vector<int> inv((size_t)p->n_tiles * 256, -1);
+    for (size_t k = 0; k < ent.size(); ++k) inv[ent[k]] = (int)k;
+    PS_TRY(upload(p, &p->closing_of_ent_d, inv));
+    if (p->jsched) {
+      std::vector<int> inv_j((size_t)p->n_tiles_j * 256, -1);
+      for (size_t k = 0; k < ent_j.size(); ++k) inv_j[ent_j[k]] = (int)k;
+      PS_TRY(upload(p, &p->closing_of_ent_j_d, inv_j));
+    }
+  }
   PS_TRY(upload(p, &p->bins_d, p->cl_bins));
   PS_TRY(upload(p, &p->fnorm_d, fnorm));
   PS_TRY(dev_alloc(p, &p->flag_d, 256));
@@ -877,7 +889,7 @@ void release(polyspec_plan_s* p) {
   p->ev_pool.clear();
   DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_lane_d, &p->slot_tile_d, &p->ent_d,
                     &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->jtile_d, &p->jmask_d,
-                    &p->ent_j_d, &p->own_ws};
+                    &p->ent_j_d, &p->closing_of_ent_d, &p->closing_of_ent_j_d, &p->own_ws};
   for (DevBuf* b : bufs) dev_free(b);
 }
 
@@ -1002,17 +1014,12 @@ static polyspec_status shell_slab(polyspec_plan_t p, int slab, unsigned* absmax_
   return POLYSPEC_OK;
 }
 
-// Per-field maxima of the shell fields (the scaling of the contraction's operands):
-// resident fields are scanned; streamed ones are computed slab by slab and dropped.
+// Per-field maxima of resident shell fields (the scaling of the contraction's operands).
 static polyspec_status field_maxima(polyspec_plan_t p) {
   const int nz = p->batch * p->nb;
   hipStream_t st = p->stream;
   PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
-  if (p->streamed) {
-    for (int k = 0; k < p->n_slabs; ++k) PS_TRY(shell_slab(p, k, p->absmax_part));
-  } else {
-    PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));
-  }
+  PS_HIP(p, ps::launch_fields_absmax(p->D, p->G, nz, p->absmax_part, ps::kAbsmaxSpreadHost, st));
   PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
   p->absmax_valid = true;
   return POLYSPEC_OK;
@@ -1038,11 +1045,7 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   PS_TIMED(p, POLYSPEC_PH_SHELL_P1, ps::launch_c2r_p1<float, false>(p->box, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
                                             (const cplx<float>*)p->tw32.p, gs, nz, st));
   p->absmax_valid = false;
-  if (p->streamed) {
-    // the fields are made slab by slab inside polyspec_contract; only their maxima
-    // are needed now, and only when the contraction scales its operands
-    if (scaled_contraction(p)) PS_TRY(field_maxima(p));
-  } else {
+  if (!p->streamed) {   // a streamed plan makes its fields slab by slab in polyspec_contract
     const bool want_max = scaled_contraction(p);
     if (want_max) PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
     PS_TRY(shell_slab(p, 0, want_max ? p->absmax_part : nullptr));
@@ -1100,8 +1103,13 @@ static polyspec_status contract_launch(polyspec_plan_t p, bool accumulate, long 
   }
   // chunk groups of red_cpg chunks; the aligned kernel has at most as many chunks
   *groups = (n_chunks + p->red_cpg - 1) / p->red_cpg;
+  // a streamed slab's operands carry the slab's own scales: removed here, per entry
+  const int* closing_of_entry = nullptr;
+  if (p->streamed && scaled_contraction(p))
+    closing_of_entry = (const int*)(*ent == (const int*)p->ent_j_d.p ? p->closing_of_ent_j_d.p : p->closing_of_ent_d.p);
   PS_TIMED(p, POLYSPEC_PH_REDUCE, ps::launch_reduce_f32(p->partials, p->red, n_chunks, p->red_cpg, *groups, *n_ent,
-                                                        accumulate, p->batch, st));
+                                                        accumulate, closing_of_entry, (const int*)p->bins_d.p,
+                                                        p->order, p->absmax, p->nb, p->prec, p->batch, st));
   return POLYSPEC_OK;
 }
 
@@ -1110,15 +1118,20 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   if (!d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null output");
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_contract before polyspec_shells");
   hipStream_t st = p->stream;
-  if (scaled_contraction(p) && !p->absmax_valid) PS_TRY(field_maxima(p));  // precision switched after shells
+  const bool scaled = scaled_contraction(p);
+  if (scaled && !p->streamed && !p->absmax_valid) PS_TRY(field_maxima(p));  // precision switched after shells
   long long n_ent = 0;
   int groups = 0;
   const int* ent = nullptr;
   if (p->streamed) {
-    // slab by slab: the slab's fields, its contraction, and its sums added in FP64 in
+    // slab by slab: the slab's fields (and, when the operands are scaled, the slab's own
+    // per-field maxima), its contraction, and its sums unscaled and added in FP64 in
     // slab order (a fixed order, so reruns are bitwise equal)
+    const int nz = p->batch * p->nb;
     for (int k = 0; k < p->n_slabs; ++k) {
-      PS_TRY(shell_slab(p, k, nullptr));
+      if (scaled) PS_HIP(p, ps::launch_fill_u32(p->absmax_part, 0u, (size_t)nz * ps::kAbsmaxSpreadHost, st));
+      PS_TRY(shell_slab(p, k, scaled ? p->absmax_part : nullptr));
+      if (scaled) PS_HIP(p, ps::launch_reduce_absmax(p->absmax_part, p->absmax, nz, st));
       PS_TRY(contract_launch(p, k > 0, &n_ent, &groups, &ent));
     }
   } else {
@@ -1129,7 +1142,8 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   const int ncl = (int)p->closing.size();
   if (ncl > 0)
     PS_TIMED(p, POLYSPEC_PH_GATHER, ps::launch_gather(p->red, groups, n_ent, ent, (const int*)p->bins_d.p,
-                                p->order, (const double*)p->fnorm_d.p, ncl, p->absmax, p->nb, p->prec, d_out,
+                                p->order, (const double*)p->fnorm_d.p, ncl, p->streamed ? nullptr : p->absmax,
+                                p->nb, p->prec, d_out,
                                 d_raw_sums, guard ? (int*)p->flag_d.p : nullptr, p->batch, st));
   if (guard) {
     int flag = 0;
