@@ -129,8 +129,8 @@ WORKLOADS = {
                                    field="lognormal", seeds=[2]),
     "pentaspec_256_lognormal": dict(N=256, order=6, n_shells=8, width=1.0, batch=1,
                                     field="lognormal", seeds=[2]),
-    # streamed mode: a 1024^3 input given as its half spectrum, the band-limited
-    # interpolation of the 512^3 field above (zero_padded_half_spectrum)
+    # streamed mode: a 1024^3 input, the band-limited interpolation of the 512^3 field
+    # above (the inverse transform of zero_padded_half_spectrum)
     "bispec_1024_streamed": dict(N=1024, order=3, n_shells=64, width=1.0, batch=1,
                                  field="lognormal", seeds=[5], spectrum_of="bispec_512_lognormal",
                                  stream=True),

@@ -135,8 +135,10 @@ polyspec_status polyspec_set_workspace(polyspec_plan_t plan, void* d_ptr, size_t
  * each slab's sums in float64, in slab order.  The fields are recomputed by every
  * polyspec_contract call; when the contraction scales its operands (FP16 split, orders
  * 5 and 6) each slab takes its own per-field maxima, and the float64 reduction of the
- * slab removes the scale.  polyspec_backward and polyspec_fields are not available on
- * such plans.
+ * slab removes the scale.  polyspec_backward runs slab by slab as well: each slab's
+ * fields are made once more, its adjoint product and the adjoint's x2 and x0
+ * transforms follow, and the x1 transform and the gradient's inverse passes run once
+ * at the end.  polyspec_fields is not available on such plans.
  * polyspec_set_slab_planes sets the slab: a power of two between the smallest slab the
  * last pass accepts (4 at N = 32, 1 above) and N; it must precede the first use of the
  * workspace (POLYSPEC_ERR_STATE after it, or on a plan without the flag).  The default

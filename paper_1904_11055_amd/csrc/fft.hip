@@ -314,7 +314,8 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3_wedge(const cplx<double>* 
 // Forward direction (real grid -> ball)
 // ---------------------------------------------------------------------------
 
-// Q3: rows in pairs, real-to-complex over x2, keep c = 0..Kc.  in[z * G + row * N + x2].
+// Q3: rows (x0, x1) of the slab in pairs, real-to-complex over x2, keep c = 0..Kc.
+// in[z * N S1 N + row * N + x2]; grid (N*S1/2/P, 1, nz).
 // grid (N*N/2/P, 1, nz)
 template <int N>
 __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ in,
@@ -327,7 +328,8 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ 
   __shared__ cplx<T> stw[stage_tw_size<N>()];
   build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
-  const size_t G = (size_t)N * N * N;
+  const size_t rows = (size_t)N * g.S1;   // rows (x0, x1) of the slab
+  const size_t G = rows * N;
   const int row0 = blockIdx.x * 2 * P;
   const float* src = in + (size_t)z * G + (size_t)row0 * N;
   constexpr int E = P * N / kFftThreads;
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ 
   }
   __syncthreads();
   fft_block<T, N, P, NS, -1>(buf, stw);
-  cplx<T>* o = H2 + (size_t)z * N * N * g.B2 + (size_t)row0 * g.B2;
+  cplx<T>* o = H2 + (size_t)z * rows * g.B2 + (size_t)row0 * g.B2;
   for (int u = threadIdx.x; u < 2 * P * g.B2; u += kFftThreads) {
     const int r = u / g.B2, c = u % g.B2;
     const int pp = r >> 1;
@@ -363,7 +365,8 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ 
   }
 }
 
-// Q2: pencils (x1, c), transform x0 -> q0, keep |q0| <= Kc.  grid (ceil(B2/P), N, nz)
+// Q2: pencils (x1, c) for the x1 planes of the slab, transform x0 -> q0, keep
+// |q0| <= Kc; writes rows x1 of the whole H1.  grid (ceil(B2/P), S1, nz)
 template <int N>
 __global__ __launch_bounds__(kFftThreads) void r2c_q2(const cplx<float>* __restrict__ H2,
                                                       cplx<float>* __restrict__ H1,
@@ -376,15 +379,16 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q2(const cplx<float>* __restr
   build_stage_twiddles<T, N>(stw, tw);
   const int z = blockIdx.z;
   const int c0 = blockIdx.x * P;
-  const int x1 = blockIdx.y;
-  const cplx<T>* in = H2 + (size_t)z * N * N * g.B2;
+  const int xs = blockIdx.y;          // plane within the slab
+  const int x1 = g.x1_0 + xs;
+  const cplx<T>* in = H2 + (size_t)z * N * g.S1 * g.B2;
   constexpr int E = P * N / kFftThreads;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x0 = u / P;
     const int c = c0 + pp;
-    buf[pp * NS + pad8(x0)] = (c < g.B2) ? in[((size_t)x0 * N + x1) * g.B2 + c] : cplx<T>{0, 0};
+    buf[pp * NS + pad8(x0)] = (c < g.B2) ? in[((size_t)x0 * g.S1 + xs) * g.B2 + c] : cplx<T>{0, 0};
   }
   __syncthreads();
   fft_block<T, N, P, NS, -1>(buf, stw);
@@ -548,7 +552,9 @@ hipError_t launch_c2r_p3_wedge(const cplx<double>* H2, const int* qmax, const in
 hipError_t launch_r2c_q3(const float* in, cplx<float>* H2, const cplx<float>* tw, Geom g, int nz,
                          hipStream_t st) {
   const int P = FftCfg<float>::kRowElems / g.N;
-  dim3 grid(g.N * g.N / 2 / P, 1, nz);
+  if (g.S1 < 1 || g.x1_0 < 0 || g.x1_0 + g.S1 > g.N || ((size_t)g.N * g.S1) % (2 * P) != 0)
+    return hipErrorInvalidValue;
+  dim3 grid((unsigned)((size_t)g.N * g.S1 / 2 / P), 1, nz);
   switch (g.N) {
 #define CASE(n) case n: hipLaunchKernelGGL((r2c_q3<n>), grid, dim3(kFftThreads), 0, st, in, H2, tw, g); break;
     PS_FOR_EACH_N(CASE)
@@ -561,7 +567,8 @@ hipError_t launch_r2c_q3(const float* in, cplx<float>* H2, const cplx<float>* tw
 hipError_t launch_r2c_q2(const cplx<float>* H2, cplx<float>* H1, const cplx<float>* tw, Geom g, int nz,
                          hipStream_t st) {
   const int P = FftCfg<float>::kElems / g.N;
-  dim3 grid((g.B2 + P - 1) / P, g.N, nz);
+  if (g.S1 < 1 || g.x1_0 < 0 || g.x1_0 + g.S1 > g.N) return hipErrorInvalidValue;
+  dim3 grid((g.B2 + P - 1) / P, g.S1, nz);
   switch (g.N) {
 #define CASE(n) case n: hipLaunchKernelGGL((r2c_q2<n>), grid, dim3(kFftThreads), 0, st, H2, H1, tw, g); break;
     PS_FOR_EACH_N(CASE)

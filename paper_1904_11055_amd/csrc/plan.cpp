@@ -112,6 +112,7 @@ struct polyspec_plan_s {
   cplx<float>* box = nullptr;
   cplx<float>* gbox = nullptr;
   cplx<float>* H1 = nullptr;
+  cplx<float>* H1a = nullptr;   // streamed backward: the adjoint's x1 rows (H1 keeps the forward's)
   cplx<float>* H2 = nullptr;
   float* D = nullptr;
   float* A = nullptr;
@@ -278,7 +279,7 @@ std::vector<cplx<T>> twiddles(int N) {
 
 // Sizes of the workspace pieces, in carving order.
 struct WsLayout {
-  size_t box, gbox, H1, H2, D, A, partials, red, absmax, W, total;
+  size_t box, gbox, H1, H1a, H2, D, A, partials, red, absmax, W, total;
 };
 
 WsLayout layout_of(const polyspec_plan_s* p) {
@@ -286,10 +287,11 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   const size_t zf = (size_t)p->batch * p->nb;
   L.box = align256((size_t)p->batch * box_elems * sizeof(cplx<float>));
-  const bool adjoint = !p->streamed && (p->order == 3 || (p->order == 4 && p->nb <= ps::kAdj4MaxShells));
+  const bool adjoint = p->order == 3 || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
   const size_t planes = p->streamed ? p->S1 : p->N;   // x1 planes held of H2 and of the fields
   L.gbox = adjoint ? L.box : 0;
   L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
+  L.H1a = (adjoint && p->streamed) ? L.H1 : 0;
   // H2 also takes the input's first transform, batch x N^2 x B2, when a slab is smaller
   L.H2 = align256(std::max(zf * p->N * planes, (size_t)p->batch * p->N * p->N) * p->B2 * sizeof(cplx<float>));
   L.D = align256(zf * (size_t)p->N * planes * p->N * sizeof(float));
@@ -302,7 +304,7 @@ WsLayout layout_of(const polyspec_plan_s* p) {
         : p->order == 3 ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16)
         : adjoint ? align256((size_t)p->batch * (p->nb * (p->nb + 1) / 2) * ps::kAdj4WordsPerItem * 16)
                   : 0;
-  L.total = L.box + L.gbox + L.H1 + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
+  L.total = L.box + L.gbox + L.H1 + L.H1a + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
   return L;
 }
 
@@ -312,6 +314,7 @@ void carve(polyspec_plan_s* p, char* base) {
   p->box = (cplx<float>*)c; c += L.box;
   p->gbox = L.gbox ? (cplx<float>*)c : nullptr; c += L.gbox;
   p->H1 = (cplx<float>*)c; c += L.H1;
+  p->H1a = L.H1a ? (cplx<float>*)c : nullptr; c += L.H1a;
   p->H2 = (cplx<float>*)c; c += L.H2;
   p->D = (float*)c; c += L.D;
   p->A = L.A ? (float*)c : nullptr; c += L.A;
@@ -1156,8 +1159,6 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
 
 polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, float* d_grad_delta) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
-  if (p->streamed)
-    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward needs resident shell fields (a plan without POLYSPEC_STREAM_SLABS)");
   if (p->order != 3 && !(p->order == 4 && p->nb <= ps::kAdj4MaxShells))
     return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward is implemented for order 3, and order 4 with at most 32 shells");
   if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM)
@@ -1175,27 +1176,51 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
     PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
              ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb,
                                         ncl, aprec, (uint4*)p->W, p->batch, st));
-    PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
-             ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G,
-                                     fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gs, p->batch, st));
   } else {
     PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
              ps::launch_adjoint4_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb,
                                          ncl, aprec, (uint4*)p->W, p->batch, st));
-    PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
-             ps::launch_adjoint4_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, p->G,
-                                      fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gs, p->batch, st));
+  }
+  // a streamed plan keeps the forward's first pass in H1 for the next slabs, so the
+  // adjoint's x1 rows go to a buffer of their own
+  cplx<float>* H1x = p->streamed ? p->H1a : p->H1;
+  // a_m on the fields in D (the whole grid, or one slab), then its x2 and x0 transforms
+  // into rows x1 of H1x
+  auto adjoint_rows = [&](int slab) -> polyspec_status {
+    Geom gk = gs;
+    if (p->streamed) {
+      gk.S1 = p->S1;
+      gk.x1_0 = slab * p->S1;
+    }
+    const long long Gk = launch_points(p);
+    if (p->order == 3)
+      PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
+               ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, Gk,
+                                       fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gk, p->batch, st));
+    else
+      PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
+               ps::launch_adjoint4_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, Gk,
+                                        fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gk, p->batch, st));
+    if (!fused) PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gk, nz, st));
+    PS_TIMED(p, POLYSPEC_PH_ADJ_Q2, ps::launch_r2c_q2(p->H2, H1x, tw, gk, nz, st));
+    return POLYSPEC_OK;
+  };
+  if (p->streamed) {
+    for (int k = 0; k < p->n_slabs; ++k) {   // the slab's fields again, then its adjoint rows
+      PS_TRY(shell_slab(p, k, nullptr));
+      PS_TRY(adjoint_rows(k));
+    }
+  } else {
+    PS_TRY(adjoint_rows(0));
   }
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   PS_HIP(p, ps::launch_fill_u32(p->gbox, 0u, (size_t)p->batch * box_elems * 2, st));
-  if (!fused) PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gs, nz, st));
-  PS_TIMED(p, POLYSPEC_PH_ADJ_Q2, ps::launch_r2c_q2(p->H2, p->H1, tw, gs, nz, st));
-  PS_TIMED(p, POLYSPEC_PH_ADJ_Q1, ps::launch_r2c_q1<true>(p->H1, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
+  PS_TIMED(p, POLYSPEC_PH_ADJ_Q1, ps::launch_r2c_q1<true>(H1x, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
                                     nz, st));
   Geom gall = make_geom(p, 0, 0);
-  PS_TIMED(p, POLYSPEC_PH_GRAD_P1, ps::launch_c2r_p1<float, false>(p->gbox, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->H1,
+  PS_TIMED(p, POLYSPEC_PH_GRAD_P1, ps::launch_c2r_p1<float, false>(p->gbox, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, H1x,
                                             tw, gall, p->batch, st));
-  PS_TIMED(p, POLYSPEC_PH_GRAD_P2, ps::launch_c2r_p2<float>(p->H1, (const int*)p->qmax_d.p, p->H2, tw, gall, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_GRAD_P2, ps::launch_c2r_p2<float>(H1x, (const int*)p->qmax_d.p, p->H2, tw, gall, p->batch, st));
   PS_TIMED(p, POLYSPEC_PH_GRAD_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, d_grad_delta, nullptr, tw, gall, p->batch, st));
   return POLYSPEC_OK;
 }

@@ -192,40 +192,56 @@ def test_high_order_256_lognormal(gpu, name, shells, precision, tol):
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
 def test_bispec_1024_streamed_interpolation(gpu, precision, tol):
-    """1024^3 in streamed mode, which the resident path cannot hold (its shell fields alone take 275 GB).
+    """1024^3 in streamed mode, forward and backward; the resident path cannot hold this size
+    (its shell fields alone take 275 GB).
 
-    The input is the 512^3 benchmark field's spectrum on the ball, times 8, on a 1024^3
-    grid (its band-limited interpolation).  The modes are the same, so the counts are
-    equal, and d_s^1024 at even points is 8 d_s^512; every product of three fields has
-    no mode beyond 3 K_e < 256, so S_1024 = 8 (8^3) S_512 and B_1024 = 8^3 B_512.
+    delta_512 is the 512^3 benchmark field restricted to the modes of the shells' box, and
+    delta_1024 its band-limited interpolation (every 512^3 mode times 8 on a 1024^3 grid).
+    The modes are the same, so the counts are equal; d_s^1024 at even points is 8 d_s^512
+    and no product of three fields has a mode beyond 3 K_e < 256, so B_1024 = 8^3 B_512.
+    For L = sum_t g_t B_t, L_1024(I delta) = 512 L_512(delta); the adjoint of the
+    interpolation I takes a band-limited field b to 8 b at the even points, so the
+    1024^3 gradient at even points is 64 times the 512^3 gradient.
     """
     import torch
     import paper_1904_11055_amd as ps
     w = fieldgen.WORKLOADS["bispec_1024_streamed"]
     nb, width, K = w["n_shells"], w["width"], 64
-    say("generating the 512^3 lognormal field and its spectra on 512^3 and 1024^3")
+    say("generating the 512^3 lognormal field and its band-limited versions on 512^3 and 1024^3")
     field = _fields_cached(w["spectrum_of"])[0]
-    hs512 = torch.from_numpy(fieldgen.zero_padded_half_spectrum(field, 512, K)[None]).to("cuda:0")
-    p512 = ps.Plan(512, 3, nb, width, precision=precision, flags=ps.INPUT_HALF_SPECTRUM, device="cuda:0")
-    p512.shells(hs512)
+
+    def real_field(n):
+        hs = torch.from_numpy(fieldgen.zero_padded_half_spectrum(field, n, K)).to("cuda:0")
+        x = torch.fft.irfftn(hs, s=(n, n, n)).to(torch.float32)[None].contiguous()
+        del hs
+        torch.cuda.empty_cache()
+        return x
+
+    rng = np.random.default_rng(7)
+    p512 = ps.Plan(512, 3, nb, width, precision=precision, device="cuda:0")
+    g = torch.from_numpy(rng.standard_normal((1, p512.n_closing))).to("cuda:0")
+    x = real_field(512)
+    p512.shells(x)
     B512 = p512.contract().cpu().numpy()
+    grad512 = p512.backward(g).cpu().numpy()
     counts512 = p512.counts.copy()
     p512.close()
-    del hs512
-    hs1024 = torch.from_numpy(fieldgen.zero_padded_half_spectrum(field, 1024, K)[None]).to("cuda:0")
-    torch.cuda.empty_cache()
+    del x
     say("1024^3 streamed plan")
-    p1024 = ps.Plan(1024, 3, nb, width, precision=precision, flags=ps.INPUT_HALF_SPECTRUM | ps.STREAM_SLABS,
-                    device="cuda:0")
+    x = real_field(1024)
+    p1024 = ps.Plan(1024, 3, nb, width, precision=precision, flags=ps.STREAM_SLABS, device="cuda:0")
     assert p1024.slab_planes < 1024
     assert np.array_equal(p1024.counts, counts512)
     _, quot = p1024.candidates()
     assert _integral(quot)
-    p1024.shells(hs1024)
+    p1024.shells(x)
     B1024 = p1024.contract().cpu().numpy()
-    rel = np.linalg.norm(B1024 - 512.0 * B512) / np.linalg.norm(512.0 * B512)
-    say(f"streamed 1024^3 ({1024 // p1024.slab_planes} slabs) vs 8^3 x resident 512^3: relative L2 {rel:.2e}")
-    assert rel < tol
+    grad1024 = p1024.backward(g)[:, ::2, ::2, ::2].cpu().numpy()
+    rel_b = np.linalg.norm(B1024 - 512.0 * B512) / np.linalg.norm(512.0 * B512)
+    rel_g = np.linalg.norm(grad1024 - 64.0 * grad512) / np.linalg.norm(64.0 * grad512)
+    say(f"streamed 1024^3 ({1024 // p1024.slab_planes} slabs) vs resident 512^3: B {rel_b:.2e}, gradient {rel_g:.2e}")
+    assert rel_b < tol
+    assert rel_g < 1e-4
     p1024.close()
 
 

@@ -203,6 +203,32 @@ def test_streamed_batch_and_smallest_slab(gpu, order, precision, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("order,N,nb,batch,planes,precision,tol", [
+    (3, 32, 8, 1, 4, 0, 1e-4), (3, 32, 8, 1, 8, 1, 1e-4), (3, 64, 12, 2, 8, 1, 1e-4), (4, 32, 7, 1, 4, 2, 1e-4)])
+def test_streamed_backward(gpu, order, N, nb, batch, planes, precision, tol):
+    """The adjoint slab by slab: against the FP64 oracle gradient and the resident plan's gradient."""
+    import torch
+    ps = _ps()
+    fields = np.stack([fieldgen.lognormal_field(N, 60 + b).astype(np.float32) for b in range(batch)])
+    rng = np.random.default_rng(order)
+    grads = {}
+    for flags, kw in ((ps.STREAM_SLABS, dict(slab_planes=planes)), (0, {})):
+        plan = ps.Plan(N, order, nb, 1.0, batch=batch, precision=precision, flags=flags, device="cuda:0", **kw)
+        g = rng.standard_normal((batch, plan.n_closing)) if not grads else grads["g"]
+        plan.shells(torch.from_numpy(fields).to("cuda:0"))
+        plan.contract()
+        grads["g"] = g
+        grads[flags] = plan.backward(torch.from_numpy(g).to("cuda:0")).cpu().numpy()
+        plan.close()
+    streamed, resident = grads[ps.STREAM_SLABS], grads[0]
+    assert _rel(streamed, resident) < 1e-6
+    for b in range(batch):
+        d64 = fields[b].astype(np.float64)
+        ref = O.polyspectrum(d64, order, nb, 1.0, return_fields=True)
+        gref = O.gradient(d64, order, nb, 1.0, grads["g"][b], result=ref)
+        assert _rel(streamed[b], gref) < tol
+
+
 def test_streamed_plan_limits(gpu):
     import torch
     ps = _ps()
@@ -220,9 +246,6 @@ def test_streamed_plan_limits(gpu):
     with pytest.raises(ps.PolyspecError) as e:
         ps.polyspec_set_slab_planes(plan.handle, 8)       # workspace already sized
     assert e.value.status == 6
-    with pytest.raises(ps.PolyspecError) as e:
-        plan.backward(torch.ones((1, plan.n_closing), dtype=torch.float64, device="cuda:0"))
-    assert e.value.status == 7
     with pytest.raises(ps.PolyspecError) as e:
         plan.fields()
     assert e.value.status == 6
