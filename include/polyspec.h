@@ -127,9 +127,10 @@ polyspec_status polyspec_workspace_size(polyspec_plan_t plan, size_t* bytes);
  * it the plan allocates its own on first use and frees it in polyspec_destroy. */
 polyspec_status polyspec_set_workspace(polyspec_plan_t plan, void* d_ptr, size_t bytes);
 
-/* Streamed mode (plans made with POLYSPEC_STREAM_SLABS).  Storing every shell field
- * takes batch * n_shells * N^3 * 4 bytes (275 GB at N = 1024 with 64 shells), more
- * than one GPU holds.  A streamed plan keeps only the ball of delta_hat and the first
+/* Streamed mode (plans made with POLYSPEC_STREAM_SLABS; the grid is processed in slabs
+ * as the paper distributes it over processes, Sec. 3, so that the grids of Sec. 4.3
+ * fit).  Storing every shell field takes batch * n_shells * N^3 * 4 bytes (275 GB at
+ * N = 1024 with 64 shells), more than one GPU holds.  A streamed plan keeps only the ball of delta_hat and the first
  * inverse pass (O(n_shells N^2 K) values); polyspec_contract then runs the last two
  * inverse passes and the contraction one slab of `planes` x1-planes at a time and adds
  * each slab's sums in float64, in slab order.  The fields are recomputed by every
@@ -204,7 +205,7 @@ polyspec_status polyspec_profile_read(polyspec_plan_t plan, double* h_ms, int64_
  * precision: every launched tile counts in full, including entries no tuple
  * needs, so this is the work the hardware does rather than the algorithmic
  * 2 flops per tuple and grid point.  Phases POLYSPEC_PH_CONTRACT and
- * POLYSPEC_PH_ADJ_GEMM (order 3) have matrix-core work; every other phase gives 0.
+ * POLYSPEC_PH_ADJ_GEMM (orders 3 and 4) have matrix-core work; every other phase gives 0.
  * Host-only; no device work. */
 polyspec_status polyspec_issued_flops(polyspec_plan_t plan, int32_t phase, double* flops);
 

@@ -4,7 +4,7 @@ Thin Python binding over ``libpolyspec.so`` (see ``include/polyspec.h``).  The
 functions named ``polyspec_*`` marshal arguments to the C calls of the same name;
 every step of the computation runs in the library's HIP kernels.  PyTorch is used
 only for device memory and the current stream.  ``Plan`` and ``polyspectrum``
-are conveniences on top (``polyspectrum`` is differentiable for order 3).
+are conveniences on top (``polyspectrum`` is differentiable for orders 3 and 4).
 
 The estimator is the FFT form of Tomlinson, Jeong & Kim (2019), Sec. 2 and
 Appendix A: B_t = sum_x prod_j d_{t_j}[x] / (N^3 n_t) over sorted shell tuples t,
@@ -311,7 +311,7 @@ class _DeviceArray:
 
 
 def polyspectrum(delta, plan: Plan):
-    """B [batch, n_closing] (float64) of delta [batch, N, N, N]; differentiable for order 3."""
+    """B [batch, n_closing] (float64) of delta [batch, N, N, N]; differentiable for orders 3 and 4."""
     import torch
 
     class _Fn(torch.autograd.Function):
