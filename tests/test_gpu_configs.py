@@ -270,7 +270,53 @@ def test_bispec_grad_128x8(gpu):
         assert np.linalg.norm(Bh[b] - ref["B"]) / np.linalg.norm(ref["B"]) < 1e-4
         gref = O.gradient(fields[b].astype(np.float64), 3, nb, width, 2.0 * (ref["B"] - T), result=ref)
         assert np.linalg.norm(g[b] - gref) / np.linalg.norm(gref) < 1e-4
+        if b == 0:
+            _central_differences_check(fields[0].astype(np.float64), ref, T, nb, width, g[0])
     plan.close()
+
+
+def _central_differences_check(delta, ref, T, nb, width, g_gpu, n_voxels=64, eps=1e-3):
+    """dL/d delta at random voxels by FP64 central differences of L = sum_t (B_t - T_t)^2.
+
+    Moving delta[y] by e adds e c_s(x - y) to every shell field (c_s the unit-shell
+    field, the same inverse transform of the mask), so each difference needs the shifted
+    unit fields and the product sums S_t(+e), S_t(-e), not new transforms.  Both sums are
+    accumulated in one pass over x0-planes, with no grid-sized temporaries.
+    """
+    N = delta.shape[0]
+    t, n_t = ref["tuples"], ref["counts"]
+    d = ref["fields"]
+    c = O.count_fields(N, nb, width)
+    norm = float(N) ** 3 * n_t
+    pairs = O.pair_list(nb)
+    pi, pj = pairs[:, 0] - 1, pairs[:, 1] - 1
+    row = {(int(a), int(b)): n for n, (a, b) in enumerate(pairs)}
+    rows = np.array([row[(int(a), int(b))] for a, b in t[:, :2]])
+    cols = t[:, 2] - 1
+    step = 8192   # points per block: the pair products stay a few MB
+
+    def sums_pm(y):
+        acc = np.zeros((2, len(pairs), nb))
+        for i0 in range(N):
+            cs = np.roll(c[:, (i0 - y[0]) % N], shift=(int(y[1]), int(y[2])), axis=(1, 2)).reshape(nb, -1)
+            blk = d[:, i0].reshape(nb, -1)
+            for x0 in range(0, N * N, step):
+                for k, sgn in enumerate((1.0, -1.0)):
+                    f = blk[:, x0:x0 + step] + (sgn * eps) * cs[:, x0:x0 + step]
+                    acc[k] += (f[pi] * f[pj]) @ f.T
+        return acc[0][rows, cols], acc[1][rows, cols]
+
+    rng = np.random.default_rng(64)
+    ys = rng.integers(0, N, size=(n_voxels, 3))
+    fd = np.empty(n_voxels)
+    say(f"central differences at {n_voxels} voxels (FP64 oracle sums)")
+    for i, y in enumerate(ys):
+        sp, sm = sums_pm(y)
+        fd[i] = (np.sum((sp / norm - T) ** 2) - np.sum((sm / norm - T) ** 2)) / (2 * eps)
+    got = g_gpu[ys[:, 0], ys[:, 1], ys[:, 2]]
+    rel = np.linalg.norm(got - fd) / np.linalg.norm(fd)
+    say(f"GPU gradient vs central differences at {n_voxels} voxels: relative L2 {rel:.2e}")
+    assert rel < 1e-4
 
 
 @pytest.mark.parametrize("precision", [1, 2])
