@@ -91,6 +91,71 @@ def test_bispectrum_ragged_shells(gpu, precision):
     plan.close()
 
 
+# Degenerate configurations: one shell, an empty shell, a field with no power in any
+# shell (the FP16 scaling then meets all-zero fields), and a resident plan on the
+# largest grid.
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
+def test_single_shell(gpu, order, precision, tol):
+    delta = fieldgen.lognormal_field(32, 70 + order).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), order, 1, 1.0)
+    plan, B, _ = _run(delta, order, 1, 1.0, precision=precision)
+    assert np.array_equal(plan.tuples, ref["tuples"]) and len(ref["tuples"]) == 1
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert _rel(B[0], ref["B"]) < tol
+    plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
+def test_empty_shell(gpu, precision, tol):
+    """Width 1/2: shell 1, (1/4 <= |q| < 3/4), holds no mode, so no tuple with it closes."""
+    assert O.shell_mode_counts(32, 6, 0.5)[0] == 0
+    delta = fieldgen.gaussian_field(32, 73).astype(np.float32)
+    ref = O.polyspectrum(delta.astype(np.float64), 3, 6, 0.5)
+    plan, B, _ = _run(delta, 3, 6, 0.5, precision=precision)
+    assert np.array_equal(plan.tuples, ref["tuples"])
+    assert np.array_equal(plan.counts, ref["counts"])
+    assert not np.any(plan.tuples == 1)              # shell 1 is in no closing tuple
+    bins, quot = plan.candidates()
+    assert np.any(bins == 1) and np.all(quot[np.any(bins == 1, axis=1)] == 0.0)
+    assert _rel(B[0], ref["B"]) < tol
+    plan.close()
+
+
+@pytest.mark.parametrize("order", [3, 5])
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_field_without_shell_power(gpu, order, precision):
+    """A constant field has power only at q = 0, which no shell holds: every B is exactly 0."""
+    ps = _ps()
+    delta = np.full((32, 32, 32), 0.75, dtype=np.float32)
+    plan, B, S = _run(delta, order, 4, 1.0, precision=precision, flags=ps.NAN_GUARD)
+    assert np.all(np.isfinite(B)) and np.all(np.abs(S) < 1e-6 * 0.75 ** order * 32 ** (3 * order))
+    _, Bz, _ = _run(np.zeros((32, 32, 32), dtype=np.float32), order, 4, 1.0, precision=precision,
+                    flags=ps.NAN_GUARD)
+    assert np.array_equal(Bz, np.zeros_like(Bz))
+    plan.close()
+
+
+def test_largest_grid_resident(gpu):
+    """N = 1024 without streaming (4 shells): the band-limited interpolation of a 256^3 field
+    gives B_1024 = (4^3)^3 B_256 with the same counts."""
+    import torch
+    ps = _ps()
+    field = fieldgen.lognormal_field(256, 74)
+    res = {}
+    for n in (256, 1024):
+        hs = torch.from_numpy(fieldgen.zero_padded_half_spectrum(field, n, 4)[None]).to("cuda:0")
+        plan = ps.Plan(n, 3, 4, 1.0, flags=ps.INPUT_HALF_SPECTRUM, device="cuda:0")
+        assert plan.slab_planes == n
+        plan.shells(hs)
+        res[n] = (plan.counts.copy(), plan.contract().cpu().numpy())
+        plan.close()
+        del hs
+        torch.cuda.empty_cache()
+    assert np.array_equal(res[1024][0], res[256][0])
+    assert _rel(res[1024][1], 64.0 ** 3 * res[256][1]) < 1e-5
+
+
 def test_unit_spectrum_gives_one(gpu):
     plan, B, _ = _run(fieldgen.unit_spectrum_field(32), 3, 10, 1.0)
     np.testing.assert_allclose(B[0], 1.0, rtol=1e-5)   # the FP32 gate
