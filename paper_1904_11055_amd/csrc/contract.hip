@@ -497,15 +497,17 @@ __global__ __launch_bounds__(kJThreads, 1) void contract_j3(CtrJParams p) {
           pre[f] = *reinterpret_cast<const float4*>(Db + (size_t)st_row[f] * p.G + x_base + (ks + 1) * kKStep +
                                                     st_col[f]);
     }
-    // the slot masks are re-read from SGPRs every step (scalar bit tests) instead of
-    // being kept as 40 precomputed lane masks, which would not fit in the SGPRs
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+    // the slot masks are re-read from SGPRs every half step (scalar bit tests) instead
+    // of being kept as 40 precomputed lane masks, which would not fit in the SGPRs: with
+    // one re-read per step the compiler still kept the 40 conditions of both halves and
+    // spilled them into VGPR lanes (51.0 -> 47.5 ms for the 512^3 contraction)
     unsigned mm0 = m0, mm1 = m1;
     asm volatile("" : "+s"(mm0), "+s"(mm1));
     mm0 = __builtin_amdgcn_readfirstlane(mm0);
     mm1 = __builtin_amdgcn_readfirstlane(mm1);
     auto active = [&](int s) { return ((s < 32 ? mm0 >> s : mm1 >> (s - 32)) & 1u) != 0; };
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
       Operand<PREC> Bop[kMaxBlk];
 #pragma unroll
       for (int kb = 0; kb < kMaxBlk; ++kb) Bop[kb] = op_from_words<PREC>(opHi[cur][h][kb][lane], opLo[cur][h][kb][lane]);
