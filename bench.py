@@ -142,8 +142,8 @@ def cpu_baseline(delta32, w, n_closing, planes: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(sharding over x0-slabs is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the grid would shard "
+              "over x0-slabs with one small all-reduce per direction).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

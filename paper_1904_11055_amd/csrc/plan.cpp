@@ -464,7 +464,11 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
     (*ent_of_cand)[c] = t * 256 + tile_entry(loc[c][2], loc[c][3]);
   }
   // units: runs of tiles sharing the A block, cut into pieces that fit one wave
-  const int cap = n == 2 ? ps::kSlots2Host : n == 3 ? ps::kSlotsHost : n == 4 ? ps::kSlots4Host : n == 5 ? ps::kSlots56Host : ps::kSlots6Host;
+  const int cap = n == 2   ? ps::kSlots2Host
+                  : n == 3 ? ps::kSlotsHost
+                  : n == 4 ? ps::kSlots4Host
+                  : n == 5 ? ps::kSlots56Host
+                           : ps::kSlots6Host;
   std::vector<std::pair<int, int>> units;  // [first tile, count]
   for (int t = 0; t < id;) {
     int u = t;
@@ -998,7 +1002,9 @@ polyspec_status polyspec_slab_planes(polyspec_plan_t p, int32_t* planes) {
 
 // The contraction scales every shell field by a power of two (from its largest
 // magnitude) for the FP16 split, and at orders 5 and 6 for every precision.
-static bool scaled_contraction(const polyspec_plan_s* p) { return p->prec == POLYSPEC_SPLIT_FP16 || p->order >= 5; }
+static bool scaled_contraction(const polyspec_plan_s* p) {
+  return p->prec == POLYSPEC_SPLIT_FP16 || p->order >= 5;
+}
 
 // Last two inverse passes for the x1-planes [x1_0, x1_0 + S1) of every shell (the whole
 // grid when not streamed), optionally with the per-field maxima.
