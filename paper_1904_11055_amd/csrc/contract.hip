@@ -240,9 +240,7 @@ __device__ __forceinline__ Operand<kFP16> form_pair_f16(const uint4 (*hi)[64], c
 // A stage holds 64 grid points (two MFMA K-steps of 32).  16 waves share one stage;
 // each wave owns up to slots_for<ORDER>() tiles.
 template <int ORDER>
-constexpr int slots_for() {
-  return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : ORDER == 4 ? kSlots4 : ORDER == 5 ? kSlots56 : kSlots6;
-}
+constexpr int slots_for() { return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : ORDER == 4 ? kSlots4 : ORDER == 5 ? kSlots56 : kSlots6; }
 
 template <int PREC, int ORDER>
 __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
