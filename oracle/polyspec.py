@@ -71,7 +71,8 @@ __all__ = [
     "shell_mode_counts", "shell_fields", "shell_fields_from_hat", "count_fields",
     "shell_fields_on_planes", "product_sums", "tuple_product_sums", "counts_from_sums", "polygon_counts",
     "pair_counts", "triple_counts", "polygon_counts_exact", "triple_list",
-    "polyspectrum", "adjoint_weights", "gradient", "physical_factor",
+    "polyspectrum", "polyspectrum_from_hat", "adjoint_weights", "gradient", "gradient_spectrum",
+    "gradient_half_spectrum", "physical_factor",
 ]
 
 
@@ -410,7 +411,19 @@ def polyspectrum(delta: np.ndarray, order: int, n_shells: int, width: float,
     B_t = physical_factor * S_t / (N^3 n_t).
     """
     delta = np.asarray(delta, dtype=np.float64)
-    N = delta.shape[0]
+    return polyspectrum_from_hat(rfftn(delta), delta.shape[0], order, n_shells, width, box_length,
+                                 allow_aliasing, counts, return_fields)
+
+
+def polyspectrum_from_hat(delta_hat: np.ndarray, N: int, order: int, n_shells: int, width: float,
+                          box_length: float = 0.0, allow_aliasing: bool = False,
+                          counts=None, return_fields: bool = False) -> dict:
+    """The estimator for a field given by its half spectrum delta_hat (rfftn layout [N, N, N//2+1]).
+
+    Appendix A's input delta[q]; the shell fields are the inverse real transforms of the
+    masked half spectrum, so in the q2 = 0 plane (where q and -q are both stored) the
+    inverse transform keeps the real part of the result, as a real-to-complex pair does.
+    """
     if 2 * outer_radius(n_shells, width) > N:
         raise ValueError("outer shell edge beyond the Nyquist wavenumber")
     alias_free = is_alias_free(N, order, n_shells, width)
@@ -424,7 +437,7 @@ def polyspectrum(delta: np.ndarray, order: int, n_shells: int, width: float,
     keep = n_cand > 0
     tuples = cand[keep]
     n_t = n_cand[keep]
-    d = shell_fields(delta, n_shells, width)
+    d = shell_fields_from_hat(np.asarray(delta_hat, dtype=np.complex128), N, n_shells, width)
     S = product_sums(d, tuples)
     B = physical_factor(order, N, box_length) * S / (float(N) ** 3 * n_t)
     out = dict(tuples=tuples, counts=n_t, sums=S, B=B, candidates=cand, candidate_counts=n_cand)
@@ -458,42 +471,83 @@ def adjoint_weights(tuples: np.ndarray, weights: np.ndarray, n_shells: int) -> n
     return W
 
 
+def gradient_spectrum(N: int, order: int, n_shells: int, width: float, tuples, counts, fields,
+                      grad_B, shells=None, box_length: float = 0.0, chunk: int = 8192) -> np.ndarray:
+    """g[q] = sum_m [s(q) = m] R2C(a_m)[q] on the rfftn layout, a_m = dL/d d_m (orders 2, 3, 4).
+
+    `fields` holds the shell fields of `shells` (all shells when None), in that order.
+    Only those a_m are formed, from products of those fields; so dL/dB_t must vanish on
+    every tuple that uses another shell (checked).
+    """
+    tuples = np.asarray(tuples, dtype=np.int64)
+    shells = list(range(1, n_shells + 1)) if shells is None else [int(s) for s in shells]
+    pos = {s: n for n, s in enumerate(shells)}
+    w = np.asarray(grad_B, dtype=np.float64) * physical_factor(order, N, box_length) \
+        / (float(N) ** 3 * np.asarray(counts, dtype=np.float64))
+    inside = np.array([all(int(v) in pos for v in t) for t in tuples], dtype=bool)
+    if np.any(w[~inside] != 0.0):
+        raise ValueError("dL/dB is non-zero on a tuple with a shell whose field is not given")
+    flat = np.asarray(fields, dtype=np.float64).reshape(len(shells), -1)
+    a = np.zeros_like(flat)
+    if order == 2:
+        # S_(i,i) = sum d_i^2; only diagonal tuples close.
+        for t, wt in zip(tuples[inside], w[inside]):
+            i, j = pos[int(t[0])], pos[int(t[1])]
+            a[i] += wt * flat[j]
+            a[j] += wt * flat[i]
+    elif order in (3, 4):
+        # a_m = sum over rests r of W[m, r] prod_{s in r} d_s, over the given shells
+        W = adjoint_weights(tuples[inside], w[inside], n_shells)
+        rests = sorted_tuples(order - 1, n_shells)
+        keep_r = np.array([all(int(v) in pos for v in r) for r in rests], dtype=bool)
+        rest_pos = np.array([[pos[int(v)] for v in r] for r in rests[keep_r]], dtype=np.int64)
+        Wk = W[np.array(shells) - 1][:, keep_r]
+        for x0 in range(0, flat.shape[1], chunk):
+            blk = flat[:, x0:x0 + chunk]
+            prod = blk[rest_pos[:, 0]].copy()
+            for c in range(1, order - 1):
+                prod *= blk[rest_pos[:, c]]
+            a[:, x0:x0 + chunk] = Wk @ prod
+    else:
+        raise ValueError("gradient supports orders 2, 3 and 4")
+    sid = shell_id_grid(N, n_shells, width)
+    g_hat = np.zeros((N, N, N // 2 + 1), dtype=np.complex128)
+    for n, m in enumerate(shells):
+        am_hat = rfftn(a[n].reshape(N, N, N))
+        sel = sid == m
+        g_hat[sel] += am_hat[sel]
+    return g_hat
+
+
 def gradient(delta: np.ndarray, order: int, n_shells: int, width: float, grad_B: np.ndarray,
              result: dict | None = None, box_length: float = 0.0,
              allow_aliasing: bool = False, chunk: int = 8192) -> np.ndarray:
-    """dL/d delta[x] for L with dL/dB_t = grad_B[t] over the closing tuples (orders 2, 3, 4)."""
+    """dL/d delta[x] for L with dL/dB_t = grad_B[t] over the closing tuples (orders 2, 3, 4).
+
+    Each d_m is C2R(M_m R2C(delta)) with an even real kernel, so the adjoint of
+    delta -> d_m is the same operator and dL/d delta = C2R(g), g = gradient_spectrum.
+    """
     delta = np.asarray(delta, dtype=np.float64)
     N = delta.shape[0]
     if result is None or "fields" not in result:
         result = polyspectrum(delta, order, n_shells, width, box_length, allow_aliasing,
                               return_fields=True)
-    tuples, n_t, d = result["tuples"], result["counts"], result["fields"]
-    w = np.asarray(grad_B, dtype=np.float64) * physical_factor(order, N, box_length) \
-        / (float(N) ** 3 * n_t)
-    flat = d.reshape(n_shells, -1)
-    a = np.zeros_like(flat)
-    if order == 2:
-        # S_(i,i) = sum d_i^2; only diagonal tuples close.
-        for t, wt in zip(tuples, w):
-            i, j = int(t[0]) - 1, int(t[1]) - 1
-            a[i] += wt * flat[j]
-            a[j] += wt * flat[i]
-    elif order in (3, 4):
-        # a_m = sum over rests r of W[m, r] prod_{s in r} d_s
-        W = adjoint_weights(tuples, w, n_shells)
-        rests = sorted_tuples(order - 1, n_shells) - 1
-        for x0 in range(0, flat.shape[1], chunk):
-            blk = flat[:, x0:x0 + chunk]
-            prod = blk[rests[:, 0]].copy()
-            for c in range(1, order - 1):
-                prod *= blk[rests[:, c]]
-            a[:, x0:x0 + chunk] = W @ prod
-    else:
-        raise ValueError("gradient supports orders 2, 3 and 4")
-    sid = shell_id_grid(N, n_shells, width)
-    g_hat = np.zeros((N, N, N // 2 + 1), dtype=np.complex128)
-    for m in range(n_shells):
-        am_hat = rfftn(a[m].reshape(N, N, N))
-        sel = sid == (m + 1)
-        g_hat[sel] += am_hat[sel]
+    g_hat = gradient_spectrum(N, order, n_shells, width, result["tuples"], result["counts"],
+                              result["fields"], grad_B, box_length=box_length, chunk=chunk)
     return irfftn(g_hat, s=(N, N, N)) * float(N) ** 3
+
+
+def gradient_half_spectrum(N: int, order: int, n_shells: int, width: float, tuples, counts, fields,
+                           grad_B, box_length: float = 0.0) -> np.ndarray:
+    """dL/dRe delta_hat + i dL/dIm delta_hat for a half-spectrum input (rfftn layout).
+
+    The inverse real transform reads an entry with q2 = 0 or q2 = N/2 once and any
+    other entry twice (itself and, conjugated, its mirror -q), so the derivative of L
+    with respect to the real and imaginary parts of that entry is 1 resp. 2 times g[q].
+    """
+    g_hat = gradient_spectrum(N, order, n_shells, width, tuples, counts, fields, grad_B,
+                              box_length=box_length)
+    wz = np.full(N // 2 + 1, 2.0)
+    wz[0] = 1.0
+    wz[N // 2] = 1.0
+    return g_hat * wz

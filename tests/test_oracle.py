@@ -384,3 +384,52 @@ def test_adjoint_weights_sum_rule():
         W = O.adjoint_weights(t, w, nb)
         assert np.isclose(W.sum(), order * w.sum())
         assert W.shape == (nb, len(O.sorted_tuples(order - 1, nb)))
+
+
+@pytest.mark.parametrize("order,nb", [(3, 4), (4, 3)])
+def test_gradient_half_spectrum_central_differences(order, nb):
+    """dL/dRe X + i dL/dIm X for a half-spectrum input X, against central differences of
+    the FP64 forward taken on X itself: modes in the q2 = 0 plane (read once by the inverse
+    real transform) and with q2 > 0 (read twice), real and imaginary parts."""
+    N = 16
+    X = O.polyspec.rfftn(fieldgen.lognormal_field(N, 51))
+    target = 0.5 * O.polyspectrum(fieldgen.lognormal_field(N, 52), order, nb, 1.0)["B"]
+    r = O.polyspectrum_from_hat(X, N, order, nb, 1.0, return_fields=True)
+    counts = r["candidate_counts"]
+    G = O.gradient_half_spectrum(N, order, nb, 1.0, r["tuples"], r["counts"], r["fields"],
+                                 2.0 * (r["B"] - target))
+
+    def loss(Xp):
+        return np.sum((O.polyspectrum_from_hat(Xp, N, order, nb, 1.0, counts=counts)["B"] - target) ** 2)
+
+    sid = O.shell_id_grid(N, nb, 1.0)
+    modes = [(1, 2, 0), (N - 2, 1, 0), (0, 1, 2), (3, N - 1, 1), (0, 0, 3), (2, 2, 2)]
+    eps = 1e-3 * np.abs(X).max()
+    scale = np.abs(G).max()
+    for m in modes:
+        assert sid[m] > 0
+        for unit in (1.0, 1j):
+            Xp = X.copy(); Xp[m] += eps * unit
+            Xm = X.copy(); Xm[m] -= eps * unit
+            fd = (loss(Xp) - loss(Xm)) / (2 * eps)
+            got = G[m].real if unit == 1.0 else G[m].imag
+            assert abs(fd - got) <= 1e-6 * scale, (m, unit, fd, got)
+
+
+def test_gradient_on_a_shell_subset_matches_full():
+    """With dL/dB zero on every tuple outside a shell subset, the gradient formed from the
+    subset's fields alone is the full gradient."""
+    N, nb, order = 16, 4, 3
+    delta = fieldgen.gaussian_field(N, 53)
+    r = O.polyspectrum(delta, order, nb, 1.0, return_fields=True)
+    sub = [1, 2, 4]
+    g = np.where([set(int(v) for v in t) <= set(sub) for t in r["tuples"]],
+                 np.linspace(1.0, 2.0, len(r["tuples"])), 0.0)
+    assert np.count_nonzero(g) > 0
+    full = O.gradient_spectrum(N, order, nb, 1.0, r["tuples"], r["counts"], r["fields"], g)
+    part = O.gradient_spectrum(N, order, nb, 1.0, r["tuples"], r["counts"],
+                               r["fields"][np.array(sub) - 1], g, shells=sub)
+    np.testing.assert_allclose(part, full, rtol=0, atol=1e-12 * np.abs(full).max())
+    with pytest.raises(ValueError):
+        O.gradient_spectrum(N, order, nb, 1.0, r["tuples"], r["counts"], r["fields"][np.array(sub) - 1],
+                            np.ones(len(r["tuples"])), shells=sub)
