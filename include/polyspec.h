@@ -74,7 +74,8 @@ typedef struct {
   int32_t N;            /* grid points per side; a power of two, 32 <= N <= 1024            */
   int32_t order;        /* n = 2 to 6 (Sec. 4.2 runs the estimator up to hexagons, n = 6)  */
   int32_t n_shells;     /* N_b >= 1; (N_b + 1/2) * width <= N/2; the matrix-core contraction
-                           handles N_b <= 64, and N_b <= 32 at orders 5 and 6                 */
+                           handles N_b <= 128 at orders 2 to 4 and N_b <= 32 at orders 5 and 6;
+                           polyspec_backward needs N_b <= 64 (order 3) or N_b <= 32 (order 4)   */
   double shell_width;   /* D > 0, in units of k_f (exact binary value is used)              */
   int32_t batch;        /* independent fields processed together, >= 1                      */
   int32_t precision;    /* polyspec_precision                                                */
@@ -109,15 +110,22 @@ polyspec_status polyspec_shells(polyspec_plan_t plan, const void* d_delta);
 polyspec_status polyspec_contract(polyspec_plan_t plan, double* d_out, double* d_raw_sums);
 
 /* Adjoint of shells + contract (not in the paper): given dL/dB_t in d_grad_out
- * (float64 [batch][n_closing]), writes dL/d delta to d_grad_delta as float32
- * [batch][N][N][N], using the shell fields of the last polyspec_shells call.
+ * (float64 [batch][n_closing]), writes the gradient with respect to the input of the
+ * last polyspec_shells call, in the same space, to d_grad_delta:
+ *  - real-space plans: dL/d delta as float32 [batch][N][N][N];
+ *  - POLYSPEC_INPUT_HALF_SPECTRUM plans: complex64 [batch][N][N][N/2+1] holding
+ *    dL/dRe delta_hat + i dL/dIm delta_hat.  An entry with q2 = 0 is read once by
+ *    the inverse real transform and an entry with 0 < q2 < N/2 twice (itself and its
+ *    conjugate mirror), so the entry is g[q] resp. 2 g[q] with g as below; entries
+ *    outside every shell are zero.
  * Each position of a closing tuple contributes dL/dB_t f/(N^3 n_t) times the
- * product of the other shell fields to a_m of its shell m; dL/d delta is the
- * unnormalised C2R of sum_m [s(q) = m] R2C(a_m).  Orders 3 and 4 (order 4 with
- * at most 32 shells); POLYSPEC_ERR_UNSUPPORTED otherwise.  Real-space input only.
- * The adjoint product runs in float32 for POLYSPEC_FP32 and as the BF16 split
- * otherwise. */
-polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out, float* d_grad_delta);
+ * product of the other shell fields to a_m of its shell m; g[q] = sum_m [s(q) = m]
+ * R2C(a_m)[q] and dL/d delta is its unnormalised C2R.  Uses the shell fields of
+ * the last polyspec_shells call; the caller must not have called polyspec_shells
+ * with another input in between (the library cannot tell).  Orders 3 and 4 (order 4
+ * with at most 32 shells, order 3 with at most 64); POLYSPEC_ERR_UNSUPPORTED otherwise.  The adjoint
+ * product runs in float32 for POLYSPEC_FP32 and in split precision otherwise. */
+polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out, void* d_grad_delta);
 
 /* Bytes of device workspace the plan needs for shells, contract and backward. */
 polyspec_status polyspec_workspace_size(polyspec_plan_t plan, size_t* bytes);

@@ -240,6 +240,20 @@ class Plan:
         self.slab_planes = polyspec_slab_planes(self.handle)
         self.tuples, self.counts = polyspec_tuples(self.handle, order)
         self.n_closing = len(self.counts)
+        self._workspace = None   # torch-allocated on the first shells() (after any slab setting)
+        self.generation = 0      # bumped by every shells(); the autograd backward checks it
+
+    def _ensure_workspace(self):
+        """Hands the library device memory from torch's allocator (256-byte aligned), once."""
+        if self._workspace is not None:
+            return
+        import torch
+        nbytes = polyspec_workspace_size(self.handle)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = ws.data_ptr()
+        polyspec_set_workspace(self.handle, base + (-base) % 256, nbytes)
+        self._workspace = ws     # the plan keeps the tensor alive
+        self.workspace_bytes = nbytes
 
     @property
     def precision(self):
@@ -265,8 +279,10 @@ class Plan:
             raise ValueError(f"expected {dt} {want} on {self.device}, got {delta.dtype} {tuple(delta.shape)} "
                              f"on {delta.device}")
         delta = delta.contiguous()
+        self._ensure_workspace()
         polyspec_shells(self.handle, delta.data_ptr())
         self._last_input = delta  # keep alive until the stream has consumed it
+        self.generation += 1
 
     def contract(self, raw=False):
         import torch
@@ -276,9 +292,16 @@ class Plan:
         return (out, rs) if raw else out
 
     def backward(self, grad_out):
+        """dL/d(input) of the last shells() input, in its space (real field or half spectrum)."""
         import torch
+        if tuple(grad_out.shape) != (self.batch, self.n_closing):
+            raise ValueError(f"grad_out must have shape {(self.batch, self.n_closing)}, got {tuple(grad_out.shape)}")
         grad_out = grad_out.to(device=self.device, dtype=torch.float64).contiguous()
-        g = torch.empty((self.batch, self.N, self.N, self.N), dtype=torch.float32, device=self.device)
+        N = self.N
+        if self.flags & INPUT_HALF_SPECTRUM:
+            g = torch.empty((self.batch, N, N, N // 2 + 1), dtype=torch.complex64, device=self.device)
+        else:
+            g = torch.empty((self.batch, N, N, N), dtype=torch.float32, device=self.device)
         polyspec_backward(self.handle, grad_out.data_ptr(), g.data_ptr())
         return g
 
@@ -292,8 +315,9 @@ class Plan:
 
     def close(self):
         if getattr(self, "handle", None):
-            polyspec_destroy(self.handle)
+            polyspec_destroy(self.handle)   # waits for the stream, then the workspace may go
             self.handle = None
+        self._workspace = None
 
     def __del__(self):
         try:
@@ -311,17 +335,28 @@ class _DeviceArray:
 
 
 def polyspectrum(delta, plan: Plan):
-    """B [batch, n_closing] (float64) of delta [batch, N, N, N]; differentiable for orders 3 and 4."""
+    """B [batch, n_closing] (float64) of delta; differentiable for orders 3 and 4.
+
+    delta is the real field [batch, N, N, N], or the half spectrum [batch, N, N, N/2+1]
+    (complex64) for plans made with INPUT_HALF_SPECTRUM; the gradient is in the same
+    space.  The plan keeps only the shell fields of its last input, so the backward of
+    a result raises if the plan has run another forward since (its fields are stale).
+    """
     import torch
 
     class _Fn(torch.autograd.Function):
         @staticmethod
         def forward(ctx, x):
             plan.shells(x.detach())
+            ctx.generation = plan.generation
             return plan.contract()
 
         @staticmethod
         def backward(ctx, g):
+            if plan.generation != ctx.generation:
+                raise RuntimeError("polyspectrum backward: the plan has run another forward since this result "
+                                   "was computed, so its shell fields belong to another input; use one plan per "
+                                   "pending backward or run the backward first")
             return plan.backward(g)
 
     return _Fn.apply(delta)

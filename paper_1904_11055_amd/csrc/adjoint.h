@@ -1,0 +1,495 @@
+// Adjoint product of the estimator (not in the paper: the gradient extension).
+//
+// Order 3: a_m[x] = sum_{u <= v} W[m][(u, v)] d_u[x] d_v[x] with
+// W[m][(u, v)] = (times m occurs in t) dL/dB_t f / (N^3 n_t), t = sort(m, u, v),
+// summed over the closing triplets t (dS_t / d d_m is the product of the other two
+// fields, once per position of m in t).
+// Order 4: a_m[x] = sum_{u <= v <= w} W4[m][(u, v, w)] d_u[x] d_v[x] d_w[x], likewise.
+//
+// Both are one matrix product per workgroup: rows m (32 per block), columns the grid
+// points, and the reduction over the row products of the other fields.  A reduction
+// step is a 16-shell chunk uc of u with the rest fixed (v, or the item (v, w)): the
+// B operand is the 16 fields d_u at the wave's 32 points times the scalar field
+// d_v (d_v d_w) at each point, formed on the VALU from fields held in registers, and
+// the A operand is the matching weight block from LDS.  The products go straight
+// into the output accumulators, so nothing on the VALU waits for a matrix result.
+//
+// Precisions: FP32 (v_mfma_f32_32x32x2_f32 on the float32 products), SPLIT_BF16
+// (products formed in float32, split hi + lo, hh + hl + lh with
+// v_mfma_f32_32x32x16_bf16), SPLIT_FP16 (v_mfma_f32_32x32x16_f16; the fields carry
+// the forward's per-shell power-of-two scale and the pair products are formed from
+// their split halves with error-free half-precision products; each weight row m
+// carries its own power of two so that its largest magnitude lies in [2^14, 2^15),
+// and the epilogue removes it exactly).
+#pragma once
+
+#include "fft_core.h"
+#include "mfma_ops.h"
+
+namespace ps {
+
+constexpr int kAdjMaxMb = 2;      // 32-row blocks of m (n_shells <= 64)
+constexpr int kAdjRowTop = 14;    // FP16: largest |W'| of a row in [2^14, 2^15)
+constexpr int kAdjWaves = 8;
+constexpr int kAdjPB = 2;                                   // 32-point column blocks per wave
+constexpr int kAdjThreads = 64 * kAdjWaves;
+constexpr int kAdjPts = 32 * kAdjPB * kAdjWaves;
+constexpr int kAdjVG = 4;
+constexpr int kAdjWPerV = 4 * kAdjMaxMb * 2 * 64;           // uint4 words of W per v
+constexpr int kAdjStageWords = kAdjVG * kAdjWPerV;
+constexpr int kAdjPiece = kAdjWPerV / kAdjThreads;          // words per thread per v step
+static_assert(kAdjPiece * kAdjThreads == kAdjWPerV, "a stage is copied in kAdjVG equal pieces");
+static_assert(kAdjPtsHost == kAdjPts, "host and device agree on the adjoint's points per workgroup");
+
+// Exponent of the power of two carried by weight row (b, m) in FP16 (0 for an empty row).
+__device__ __forceinline__ int adj_row_exp(const unsigned long long* rowmax, int idx) {
+  const double m = __longlong_as_double((long long)rowmax[idx]);
+  if (!(m > 0.0)) return 0;
+  return kAdjRowTop - ilogb(m);
+}
+
+template <int NF>
+constexpr int adj_pencils() { return NF ? 32 * (kAdjPts / NF) : 0; }
+template <int NF>
+constexpr size_t adj_fft_lds_bytes() {
+  return NF ? ((size_t)adj_pencils<NF>() * pencil_stride<NF>() + stage_tw_size<NF>()) * sizeof(cplx<float>) : 0;
+}
+template <int NF>
+constexpr size_t adj_lds_bytes() {
+  const size_t stage = (size_t)2 * kAdjStageWords * sizeof(uint4);
+  return adj_fft_lds_bytes<NF>() > stage ? adj_fft_lds_bytes<NF>() : stage;
+}
+template <int NF>
+constexpr size_t adj4_lds_bytes() {
+  const size_t stage = (size_t)kAdj4MaxShells * kAdj4WordsPerItem * sizeof(uint4);   // the items of one w
+  return adj_fft_lds_bytes<NF>() > stage ? adj_fft_lds_bytes<NF>() : stage;
+}
+
+// Writes the accumulated adjoint fields: acc[pb][mb] of lane l, register i is row
+// m = 32 mb + 8 (i / 4) + 4 (l / 32) + i % 4 at point l % 32 of column block pb.
+// Fused form (NF = N <= 512): the workgroup's 512 points are 512 / N whole rows of x2,
+// so the rows are transformed to the half spectrum q2 = 0..Kc right here (two rows m
+// per complex FFT, the same real-to-complex pass as the backward's first transform)
+// and written to H2; the fields never reach HBM.  NF = 0 writes a_m to A.
+template <int NF>
+__device__ __forceinline__ void adjoint_epilogue(const f32x16 (&acc)[kAdjPB][kAdjMaxMb], unsigned char* lds, int lane,
+                                                 int wave, int hh, int col, int b, long long xw, int n_shells,
+                                                 long long G, float* __restrict__ A, cplx<float>* __restrict__ H2,
+                                                 const cplx<float>* __restrict__ tw, const Geom& g) {
+  if constexpr (NF == 0) {
+    float* Ab = A + (size_t)b * n_shells * G + xw;
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) {
+#pragma unroll
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+          if (m < n_shells) Ab[(size_t)m * G + 32 * pb] = acc[pb][mb][i];
+        }
+      }
+    }
+  } else {
+    constexpr int P = adj_pencils<NF>();          // pencil rho * 32 + m / 2 holds rows m, m + 1 of x2-row rho
+    constexpr int NS = pencil_stride<NF>();
+    cplx<float>* buf = reinterpret_cast<cplx<float>*>(lds);
+    cplx<float>* stw = buf + P * NS;
+    __syncthreads();                              // every wave is done with the weight stages
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) {
+      const int x = wave * 32 * kAdjPB + 32 * pb + col;   // point within the workgroup
+      const int rho = x / NF, x2 = x % NF;
+#pragma unroll
+      for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+          float* slot = reinterpret_cast<float*>(&buf[(rho * 32 + (m >> 1)) * NS + pad8(x2)]);
+          slot[m & 1] = acc[pb][mb][i];
+        }
+      }
+    }
+    build_stage_twiddles<float, NF, kAdjThreads>(stw, tw);
+    __syncthreads();
+    fft_block<float, NF, P, NS, -1, kAdjThreads>(buf, stw);
+    // half spectrum of each real row: A = (Z[c] + conj Z[-c]) / 2 (row m), B = (Z[c] - conj Z[-c]) / 2i (row m + 1)
+    const long long row0 = (long long)blockIdx.x * (kAdjPts / NF);
+    for (int u = threadIdx.x; u < 2 * P * g.B2; u += kAdjThreads) {
+      const int r = u / g.B2, c = u % g.B2;
+      const int pen = r >> 1;
+      const int m = 2 * (pen & 31) + (r & 1), rho = pen >> 5;
+      if (m >= n_shells) continue;
+      const cplx<float> Zp = buf[pen * NS + pad8(c)];
+      const cplx<float> Zm = buf[pen * NS + pad8((NF - c) & (NF - 1))];
+      cplx<float> v;
+      if ((r & 1) == 0) v = cplx<float>{0.5f * (Zp.re + Zm.re), 0.5f * (Zp.im - Zm.im)};
+      else v = cplx<float>{0.5f * (Zp.im + Zm.im), 0.5f * (Zm.re - Zp.re)};
+      H2[((size_t)(b * n_shells + m) * (G / NF) + row0 + rho) * g.B2 + c] = v;   // G / NF rows per field
+    }
+  }
+}
+
+// The fields of the lane's points: shells u = 16 uc + 8 hh + r, r = 0..7, of column
+// block pb, as float32 (F, for the FP32 and BF16 paths) or as FP16 split operands of
+// the scaled values (H, for the FP16 path).
+template <int PREC, int NC>
+struct AdjFields {
+  float F[kAdjPB][NC][8];
+};
+template <int NC>
+struct AdjFields<kFP16, NC> {
+  Operand<kFP16> H[kAdjPB][NC];
+};
+
+template <int PREC, int NC>
+__device__ __forceinline__ void adj_load_fields(AdjFields<PREC, NC>& f, const float* __restrict__ Db, long long G,
+                                                long long xw, int hh, int n_shells, const unsigned* absmax,
+                                                int b) {
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb) {
+#pragma unroll
+    for (int uc = 0; uc < NC; ++uc) {
+      float x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int sh = 16 * uc + 8 * hh + r;
+        x[r] = sh < n_shells ? Db[(size_t)sh * G + xw + 32 * pb] : 0.f;
+      }
+      if constexpr (PREC == kFP16) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int sh = 16 * uc + 8 * hh + r;
+          if (sh < n_shells) x[r] = ldexpf(x[r], shell_scale_exp(absmax, b * n_shells + sh));
+        }
+        f.H[pb][uc] = make_operand<kFP16>(x, 1.f);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) f.F[pb][uc][r] = x[r];
+      }
+    }
+  }
+}
+
+// The scalar field s at this lane's point of column block pb, for the shell v = 16 vc
+// + vv held in register vv % 8 of the lanes of half vv / 8 (one permlane32 swap
+// brings the other half's value).  FP16: s holds (hi, lo) of the scaled value as the
+// halves of one 32-bit word.
+template <int PREC, int NC, int VC, int VV>
+__device__ __forceinline__ unsigned adj_scalar(const AdjFields<PREC, NC>& f, int pb) {
+  unsigned own;
+  if constexpr (PREC == kFP16) {
+    // the elements are copied out before the bit cast: the cast applied directly to a
+    // vector subscript compiles to element 0 whatever the index (hipcc, gfx950)
+    const _Float16 eh = f.H[pb][VC].hi[VV % 8];
+    const _Float16 el = f.H[pb][VC].lo[VV % 8];
+    own = (unsigned)__builtin_bit_cast(unsigned short, eh) | ((unsigned)__builtin_bit_cast(unsigned short, el) << 16);
+  } else {
+    own = __float_as_uint(f.F[pb][VC][VV % 8]);
+  }
+  const auto sw = __builtin_amdgcn_permlane32_swap(own, own, false, false);
+  return VV / 8 == 0 ? sw[0] : sw[1];
+}
+
+// B operand: fields of chunk uc at this lane's points times the scalar s (bits from
+// adj_scalar, or an FP16 split pair already scaled).
+template <int PREC, int NC>
+__device__ __forceinline__ Operand<PREC> adj_pair_operand(const AdjFields<PREC, NC>& f, int pb, int uc, unsigned s) {
+  if constexpr (PREC == kFP16) {
+    Operand<kFP16> sv;
+    const _Float16 sh = __builtin_bit_cast(_Float16, (unsigned short)(s & 0xffffu));
+    const _Float16 sl = __builtin_bit_cast(_Float16, (unsigned short)(s >> 16));
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      sv.hi[r] = sh;
+      sv.lo[r] = sl;
+    }
+    return pair_f16(f.H[pb][uc], sv);
+  } else {
+    const float sf = __uint_as_float(s);
+    float x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = f.F[pb][uc][r] * sf;
+    return make_operand<PREC>(x, 1.f);
+  }
+}
+
+// Product of two scalar fields as an FP16 split pair (error-free product of the split
+// halves) times 2^-shift, packed like adj_scalar's words.
+__device__ __forceinline__ unsigned f16_scalar_product(unsigned a, unsigned b, int shift) {
+  const _Float16 ah = __builtin_bit_cast(_Float16, (unsigned short)(a & 0xffffu));
+  const _Float16 al = __builtin_bit_cast(_Float16, (unsigned short)(a >> 16));
+  const _Float16 bh = __builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+  const _Float16 bl = __builtin_bit_cast(_Float16, (unsigned short)(b >> 16));
+  const _Float16 sc = (_Float16)ldexpf(1.0f, -shift);
+  _Float16 ph = ah * bh;
+  const _Float16 e = __builtin_fmaf16(ah, bh, -ph);
+  _Float16 pl = __builtin_fmaf16(ah, bl, __builtin_fmaf16(al, bh, e));
+  ph = ph * sc;   // a power of two: exact while in the normal range
+  pl = pl * sc;
+  return (unsigned)__builtin_bit_cast(unsigned short, ph) | ((unsigned)__builtin_bit_cast(unsigned short, pl) << 16);
+}
+
+template <int PREC>
+__device__ __forceinline__ void adj_mma(f32x16& acc, const Operand<PREC>& a, const Operand<PREC>& b) {
+  if constexpr (PREC == kFP16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.hi, b.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.lo, b.hi, acc, 0, 0, 0);
+  } else {
+    mma32<PREC>(acc, a, b);
+  }
+}
+
+// FP16: multiply every accumulated row by 2^-e_m (the weight row's scale).
+template <int PREC>
+__device__ __forceinline__ void adj_unscale(f32x16 (&acc)[kAdjPB][kAdjMaxMb], const unsigned long long* rowmax,
+                                            int b, int hh) {
+  if constexpr (PREC == kFP16) {
+#pragma unroll
+    for (int mb = 0; mb < kAdjMaxMb; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = mb * 32 + 8 * (i / 4) + 4 * hh + (i % 4);
+        const int e = adj_row_exp(rowmax, b * 64 + m);
+#pragma unroll
+        for (int pb = 0; pb < kAdjPB; ++pb) acc[pb][mb][i] = ldexpf(acc[pb][mb][i], -e);
+      }
+    }
+  }
+}
+
+// Order 3.  A workgroup of 8 waves owns 512 grid points (each wave two 32-point
+// column blocks) and every m.  The weight operands of kAdjVG values of v at a time are
+// staged in LDS, double buffered: while one stage is in use the next one is copied in,
+// a piece per v, with one barrier per stage.  Each weight block read from LDS feeds
+// both column blocks.  Values of v without any weight (vmask) are skipped.
+// MBN: 32-row blocks of m that can hold a weight (1 when n_shells <= 32, else 2).
+template <int PREC, int NF, int MBN>
+__global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __restrict__ D,
+                                                             const uint4* __restrict__ W,
+                                                             const int* __restrict__ vmask,
+                                                             const unsigned* __restrict__ absmax,
+                                                             const unsigned long long* __restrict__ rowmax,
+                                                             int n_shells, long long G, float* __restrict__ A,
+                                                             cplx<float>* __restrict__ H2,
+                                                             const cplx<float>* __restrict__ tw, Geom g) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[adj_lds_bytes<NF>()];
+  auto wst = reinterpret_cast<uint4(*)[kAdjStageWords]>(lds);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hh = lane >> 5, col = lane & 31;
+  const int b = blockIdx.y;
+  const long long xw = (long long)blockIdx.x * kAdjPts + wave * 32 * kAdjPB + col;
+  const float* Db = D + (size_t)b * n_shells * G;
+
+  AdjFields<PREC, 4> f;
+  adj_load_fields<PREC, 4>(f, Db, G, xw, hh, n_shells, absmax, b);
+
+  // v with any weight, as a 64-bit mask in scalar registers (one ballot of the per-v masks)
+  const unsigned long long vany = __ballot(lane < n_shells && vmask[lane] != 0);
+
+  const uint4* Wb = W + (size_t)b * n_shells * kAdjWPerV;
+  const int n_stages = (n_shells + kAdjVG - 1) / kAdjVG;
+  uint4 wp[kAdjPiece];
+  // piece q of stage s: words (q kAdjPiece + k) kAdjThreads + tid of the stage
+  auto w_load = [&](int s, int q) {
+#pragma unroll
+    for (int k = 0; k < kAdjPiece; ++k) {
+      const int i = (q * kAdjPiece + k) * kAdjThreads + tid;
+      const int v = s * kAdjVG + i / kAdjWPerV;
+      wp[k] = v < n_shells ? Wb[(size_t)s * kAdjStageWords + i] : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto w_store = [&](int buf, int q) {
+#pragma unroll
+    for (int k = 0; k < kAdjPiece; ++k) wst[buf][(q * kAdjPiece + k) * kAdjThreads + tid] = wp[k];
+  };
+  for (int q = 0; q < kAdjVG; ++q) {
+    w_load(0, q);
+    w_store(0, q);
+  }
+  __syncthreads();
+
+  f32x16 acc[kAdjPB][kAdjMaxMb];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+    for (int mb = 0; mb < kAdjMaxMb; ++mb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[pb][mb][i] = 0.f;
+
+  static_for<4>([&](auto vcc) {            // static v: register indices stay compile-time
+    constexpr int vc = decltype(vcc)::value;
+    if (16 * vc >= n_shells) return;
+    static_for<16>([&](auto vvc) {
+      constexpr int vv = decltype(vvc)::value;
+      const int v = 16 * vc + vv;
+      if (v >= n_shells) return;
+      const int st = v / kAdjVG, vi = v % kAdjVG;
+      const bool more = st + 1 < n_stages;
+      if (more) {                 // copy the next stage in, one piece per v
+        if (vi > 0) w_store((st + 1) & 1, vi - 1);
+        w_load(st + 1, vi);
+      }
+      // every (uc <= vc, mb < MBN) block runs without a branch (blocks without a closing
+      // tuple hold zero weights), so that the pair formation of one block and the matrix
+      // products of the others sit in one basic block and can overlap
+      if ((vany >> v) & 1ull) {
+        const uint4* wv = wst[st & 1] + vi * kAdjWPerV;
+        unsigned s[kAdjPB];
+#pragma unroll
+        for (int pb = 0; pb < kAdjPB; ++pb) s[pb] = adj_scalar<PREC, 4, vc, vv>(f, pb);
+        static_for<vc + 1>([&](auto ucc) {
+          constexpr int uc = decltype(ucc)::value;
+          Operand<PREC> P[kAdjPB];
+#pragma unroll
+          for (int pb = 0; pb < kAdjPB; ++pb) P[pb] = adj_pair_operand<PREC, 4>(f, pb, uc, s[pb]);
+#pragma unroll
+          for (int mb = 0; mb < MBN; ++mb) {
+            const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
+            const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
+#pragma unroll
+            for (int pb = 0; pb < kAdjPB; ++pb) adj_mma<PREC>(acc[pb][mb], Wop, P[pb]);
+          }
+        });
+      }
+      if (more && (vi == kAdjVG - 1)) {
+        w_store((st + 1) & 1, kAdjVG - 1);
+        __syncthreads();          // the next stage is complete; this one is free
+      }
+    });
+  });
+  adj_unscale<PREC>(acc, rowmax, b, hh);
+  adjoint_epilogue<NF>(acc, lds, lane, wave, hh, col, b, xw, n_shells, G, A, H2, tw, g);
+}
+
+// Order 4 (at most 32 shells, one 32-row block of m).  Items (w, v <= w) in order of w;
+// for each w the weights of its items are staged in LDS, and for each item the B
+// operand is d_u (chunk uc <= v / 16) times the scalar d_v d_w (FP16: times 2^-7, so
+// that the triple products of scaled fields stay below 2^14).
+template <int PREC, int NF>
+__global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __restrict__ D,
+                                                              const uint4* __restrict__ W,
+                                                              const int* __restrict__ imask,
+                                                              const unsigned* __restrict__ absmax,
+                                                              const unsigned long long* __restrict__ rowmax,
+                                                              int n_shells, long long G, float* __restrict__ A,
+                                                              cplx<float>* __restrict__ H2,
+                                                              const cplx<float>* __restrict__ tw, Geom g) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[adj4_lds_bytes<NF>()];
+  uint4* wst = reinterpret_cast<uint4*>(lds);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hh = lane >> 5, col = lane & 31;
+  const int b = blockIdx.y;
+  const long long xw = (long long)blockIdx.x * kAdjPts + wave * 32 * kAdjPB + col;
+  const float* Db = D + (size_t)b * n_shells * G;
+  const int n_items = n_shells * (n_shells + 1) / 2;
+  const uint4* Wb = W + (size_t)b * n_items * kAdj4WordsPerItem;
+
+  AdjFields<PREC, 2> f;
+  adj_load_fields<PREC, 2>(f, Db, G, xw, hh, n_shells, absmax, b);
+  f32x16 acc[kAdjPB][kAdjMaxMb];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+    for (int mb = 0; mb < kAdjMaxMb; ++mb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[pb][mb][i] = 0.f;
+
+  for (int w = 0; w < n_shells; ++w) {
+    const int it0 = w * (w + 1) / 2;
+    __syncthreads();                              // the previous w's stage is consumed
+    for (int i = tid; i < (w + 1) * kAdj4WordsPerItem; i += kAdjThreads) wst[i] = Wb[(size_t)it0 * kAdj4WordsPerItem + i];
+    // d_w at the lane's points (FP16: scaled and split like the register fields)
+    unsigned sw_[kAdjPB];
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb) {
+      const float x = Db[(size_t)w * G + xw + 32 * pb];
+      if constexpr (PREC == kFP16) {
+        const float y = ldexpf(x, shell_scale_exp(absmax, b * n_shells + w));
+        const _Float16 h = (_Float16)y;
+        const _Float16 l = (_Float16)(y - (float)h);
+        sw_[pb] = (unsigned)__builtin_bit_cast(unsigned short, h) | ((unsigned)__builtin_bit_cast(unsigned short, l) << 16);
+      } else {
+        sw_[pb] = __float_as_uint(x);
+      }
+    }
+    const int my_mask = lane <= w ? imask[it0 + lane] : 0;   // items (w, v = lane)
+    __syncthreads();
+    static_for<2>([&](auto vcc) {
+      constexpr int vc = decltype(vcc)::value;
+      static_for<16>([&](auto vvc) {
+        constexpr int vv = decltype(vvc)::value;
+        const int v = 16 * vc + vv;
+        if (v > w) return;
+        const int mask = __builtin_amdgcn_readlane(my_mask, v);   // bit uc
+        if (!mask) return;
+        const uint4* wv = wst + v * kAdj4WordsPerItem;
+        unsigned s[kAdjPB];
+#pragma unroll
+        for (int pb = 0; pb < kAdjPB; ++pb) {
+          const unsigned dv = adj_scalar<PREC, 2, vc, vv>(f, pb);
+          if constexpr (PREC == kFP16) s[pb] = f16_scalar_product(dv, sw_[pb], kTripleShift);
+          else s[pb] = __float_as_uint(__uint_as_float(dv) * __uint_as_float(sw_[pb]));
+        }
+        static_for<vc + 1>([&](auto ucc) {
+          constexpr int uc = decltype(ucc)::value;   // no branch per chunk (zero weights where empty)
+          const Operand<PREC> Wop = op_from_words<PREC>(wv[uc * 128 + lane], wv[uc * 128 + 64 + lane]);
+#pragma unroll
+          for (int pb = 0; pb < kAdjPB; ++pb) {
+            const Operand<PREC> P = adj_pair_operand<PREC, 2>(f, pb, uc, s[pb]);
+            adj_mma<PREC>(acc[pb][0], Wop, P);
+          }
+        });
+      });
+    });
+  }
+  adj_unscale<PREC>(acc, rowmax, b, hh);
+  __syncthreads();
+  adjoint_epilogue<NF>(acc, lds, lane, wave, hh, col, b, xw, n_shells, G, A, H2, tw, g);
+}
+
+template <int PREC>
+hipError_t launch_adjoint_gemm_prec(const float* D, const uint4* W, const int* vmask, const unsigned* absmax,
+                                    const unsigned long long* rowmax, int n_shells, long long G, float* A,
+                                    cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st) {
+  dim3 grid((unsigned)(G / kAdjPts), batch);
+#define L2(NF, MBN) hipLaunchKernelGGL((adjoint_gemm<PREC, NF, MBN>), grid, dim3(kAdjThreads), 0, st, D, W, vmask, \
+                                       absmax, rowmax, n_shells, G, A, H2, tw, g)
+#define L(NF) do { if (n_shells > 32) L2(NF, 2); else L2(NF, 1); } while (0)
+  switch (g.N) {
+    case 32: L(32); break;
+    case 64: L(64); break;
+    case 128: L(128); break;
+    case 256: L(256); break;
+    case 512: L(512); break;
+    default: L(0); break;
+  }
+#undef L
+#undef L2
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_adjoint4_gemm_prec(const float* D, const uint4* W, const int* imask, const unsigned* absmax,
+                                     const unsigned long long* rowmax, int n_shells, long long G, float* A,
+                                     cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st) {
+  dim3 grid((unsigned)(G / kAdjPts), batch);
+#define L(NF) hipLaunchKernelGGL((adjoint4_gemm<PREC, NF>), grid, dim3(kAdjThreads), 0, st, D, W, imask, absmax, \
+                                 rowmax, n_shells, G, A, H2, tw, g)
+  switch (g.N) {
+    case 32: L(32); break;
+    case 64: L(64); break;
+    case 128: L(128); break;
+    case 256: L(256); break;
+    case 512: L(512); break;
+    default: L(0); break;
+  }
+#undef L
+  return hipGetLastError();
+}
+
+}  // namespace ps

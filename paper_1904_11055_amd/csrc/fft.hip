@@ -485,6 +485,34 @@ __global__ void box_from_half_spectrum(const cplx<float>* __restrict__ hs, cplx<
   box[b * box_sz + i] = hs[(size_t)b * N * N * (N / 2 + 1) + src];
 }
 
+// Gradient with respect to a half-spectrum input X[q0][q1][c] (complex64
+// [batch][N][N][N/2+1]) from the ball box g of sum_m [s(q) = m] R2C(a_m)[q].  The
+// inverse real transform reads X[q] once for c = 0 and, through its conjugate mirror,
+// twice for 0 < c < N/2, so dL/dRe X + i dL/dIm X = w_c g[q] with w_0 = 1 and w_c = 2
+// (the box never reaches c = N/2).  Every output element is written: zero outside
+// the box.
+__global__ void half_spectrum_from_box(const cplx<float>* __restrict__ box, cplx<float>* __restrict__ hs, Geom g) {
+  const int N = g.N, H = N / 2 + 1;
+  const size_t per = (size_t)N * N * H;
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= per) return;
+  const int c = (int)(i % H);
+  const int i1 = (int)((i / H) % N);
+  const int i0 = (int)(i / ((size_t)H * N));
+  const int q0 = freq_of(i0, N), q1 = freq_of(i1, N);
+  cplx<float> v{0.f, 0.f};
+  if (c <= g.Kc && q0 >= -g.Kc && q0 <= g.Kc && q1 >= -g.Kc && q1 <= g.Kc) {
+    const size_t box_sz = (size_t)g.B0 * g.B2 * g.B0;
+    v = box[(size_t)b * box_sz + ((size_t)(q0 + g.Kc) * g.B2 + c) * g.B0 + (q1 + g.Kc)];
+    if (c > 0) {
+      v.re *= 2.f;
+      v.im *= 2.f;
+    }
+  }
+  hs[(size_t)b * per + i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -631,6 +659,14 @@ hipError_t launch_box_from_half_spectrum(const cplx<float>* hs, cplx<float>* box
   const size_t box_sz = (size_t)g.B0 * g.B2 * g.B0;
   dim3 grid((unsigned)((box_sz + 255) / 256), batch);
   hipLaunchKernelGGL(box_from_half_spectrum, grid, dim3(256), 0, st, hs, box, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_spectrum_from_box(const cplx<float>* box, cplx<float>* hs, Geom g, int batch,
+                                         hipStream_t st) {
+  const size_t per = (size_t)g.N * g.N * (g.N / 2 + 1);
+  dim3 grid((unsigned)((per + 255) / 256), batch);
+  hipLaunchKernelGGL(half_spectrum_from_box, grid, dim3(256), 0, st, box, hs, g);
   return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ constexpr int kAbsmaxSpreadHost = 256;
 hipError_t launch_reduce_absmax(const unsigned* part, unsigned* absmax, int nz, hipStream_t st);
 hipError_t launch_box_from_half_spectrum(const cplx<float>* hs, cplx<float>* box, Geom g, int batch,
                                          hipStream_t st);
+hipError_t launch_half_spectrum_from_box(const cplx<float>* box, cplx<float>* hs, Geom g, int batch,
+                                         hipStream_t st);
 
 // contract.hip
 struct CtrParams {
@@ -58,7 +60,8 @@ constexpr int kMaxShells56 = 32;    // orders 5 and 6: shells per plan (row tabl
 constexpr int kSlots2Host = 4;
 constexpr int kSlotsMaxHost = 16;   // per-wave stride of the slot tables
 constexpr int kStagePtsHost = 64;
-constexpr int kMaxBlkHost = 4;
+constexpr int kMaxBlkHost = 4;       // the shell-block aligned order-3 kernel (<= 64 shells)
+constexpr int kMaxTileBlkHost = 8;   // the tile kernel, orders 2 to 4 (<= 128 shells)
 constexpr int kAdjPtsHost = 512;   // grid points per adjoint workgroup
 constexpr int kCntTuplesPerGroup = 1024;
 constexpr int kCntStageHost = 32;
@@ -102,20 +105,28 @@ hipError_t launch_counts_wedge(int order, const double* cw, long long nwedge, co
                                double2* part, hipStream_t st);
 hipError_t launch_reduce_dd(const double2* part, double2* tmp, int n_chunks, int cpg, int n_groups, long long n_ent,
                             hipStream_t st);
+// Adjoint products (adjoint.h).  FP16 (prec 2) scales every weight row m by its own
+// power of two, found from rowmax[b][64] (float64 bits, written by the weights launch);
+// absmax holds the per-shell field maxima of the forward's FP16 scaling.
 hipError_t launch_adjoint_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
-                                  int n_closing, int prec, uint4* W, int batch, hipStream_t st);
+                                  int n_closing, int prec, const unsigned* absmax, unsigned long long* rowmax,
+                                  uint4* W, int batch, hipStream_t st);
 // N <= 512: the adjoint kernel also runs the first (x2 -> q2) transform of its fields
 // and writes H2 (A must be null); otherwise it writes the fields to A (H2 null).
 inline bool adjoint_fuses_rows(int N) { return N <= 512; }
-hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, int n_shells, long long G,
-                               float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
+hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, const unsigned* absmax,
+                               const unsigned long long* rowmax, int n_shells, long long G, float* A,
+                               cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
 // Order 4 (n_shells <= kAdj4MaxShells): W4[b][item (w, v <= w)][uc][hi, lo][lane], item = w (w + 1) / 2 + v.
 constexpr int kAdj4MaxShells = 32;
+constexpr int kAdj3MaxShells = 64;
 constexpr int kAdj4WordsPerItem = 2 * 2 * 64;
 hipError_t launch_adjoint4_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
-                                   int n_closing, int prec, uint4* W, int batch, hipStream_t st);
-hipError_t launch_adjoint4_gemm(int prec, const float* D, const uint4* W, const int* imask, int n_shells, long long G,
-                                float* A, cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
+                                   int n_closing, int prec, const unsigned* absmax, unsigned long long* rowmax,
+                                   uint4* W, int batch, hipStream_t st);
+hipError_t launch_adjoint4_gemm(int prec, const float* D, const uint4* W, const int* imask, const unsigned* absmax,
+                                const unsigned long long* rowmax, int n_shells, long long G, float* A,
+                                cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
 
 // util.hip
 hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_t st);

@@ -122,6 +122,7 @@ struct polyspec_plan_s {
   unsigned* absmax_part = nullptr;  // partial maxima written by the shell transform
   bool absmax_valid = false;
   float* W = nullptr;
+  unsigned long long* rowmax = nullptr;   // adjoint, FP16: per weight row maximum (float64 bits)
   bool have_fields = false;
 
   // per-kernel timing with HIP events on the plan's stream
@@ -217,6 +218,11 @@ hipEvent_t ev_get(polyspec_plan_s* p) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The adjoint product exists for order 3 up to 64 shells and order 4 up to 32.
+bool has_adjoint(const polyspec_plan_s* p) {
+  return (p->order == 3 && p->nb <= ps::kAdj3MaxShells) || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
+}
+
 Geom make_geom(const polyspec_plan_s* p, int spb, int shell_base) {
   Geom g;
   g.N = p->N;
@@ -279,7 +285,7 @@ std::vector<cplx<T>> twiddles(int N) {
 
 // Sizes of the workspace pieces, in carving order.
 struct WsLayout {
-  size_t box, gbox, H1, H1a, H2, D, A, partials, red, absmax, W, total;
+  size_t box, gbox, H1, H1a, H2, D, A, partials, red, absmax, W, rowmax, total;
 };
 
 WsLayout layout_of(const polyspec_plan_s* p) {
@@ -287,7 +293,7 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   const size_t box_elems = (size_t)p->B0 * p->B2 * p->B0;
   const size_t zf = (size_t)p->batch * p->nb;
   L.box = align256((size_t)p->batch * box_elems * sizeof(cplx<float>));
-  const bool adjoint = p->order == 3 || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
+  const bool adjoint = has_adjoint(p);
   const size_t planes = p->streamed ? p->S1 : p->N;   // x1 planes held of H2 and of the fields
   L.gbox = adjoint ? L.box : 0;
   L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
@@ -304,7 +310,8 @@ WsLayout layout_of(const polyspec_plan_s* p) {
         : p->order == 3 ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16)
         : adjoint ? align256((size_t)p->batch * (p->nb * (p->nb + 1) / 2) * ps::kAdj4WordsPerItem * 16)
                   : 0;
-  L.total = L.box + L.gbox + L.H1 + L.H1a + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W;
+  L.rowmax = adjoint ? align256((size_t)p->batch * 64 * sizeof(unsigned long long)) : 0;
+  L.total = L.box + L.gbox + L.H1 + L.H1a + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W + L.rowmax;
   return L;
 }
 
@@ -324,6 +331,7 @@ void carve(polyspec_plan_s* p, char* base) {
   p->absmax_part = (unsigned*)(c + align256((size_t)p->batch * p->nb * sizeof(unsigned)));
   c += L.absmax;
   p->W = L.W ? (float*)c : nullptr; c += L.W;
+  p->rowmax = L.rowmax ? (unsigned long long*)c : nullptr; c += L.rowmax;
 }
 
 polyspec_status ensure_workspace(polyspec_plan_s* p) {
@@ -529,7 +537,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
           const TileKey k = tlist[tl[s]];
           const int form = k.a != prev_a ? 1 : 0;
           prev_a = k.a;
-          info = (n >= 4 ? 0 : (k.b & 3)) | (n == 2 ? (k.a & 3) << 2 : 0) | (form << 4);
+          info = (n >= 4 ? 0 : (k.b & 7)) | (n == 2 ? (k.a & 7) << 3 : 0) | (form << 6);
           slot_tile[gw * S + s] = tl[s];
           for (int r = 0; r < 16; ++r) {
             int* row_words = &lanew[(gw * 16 + r) * S];
@@ -751,8 +759,8 @@ polyspec_status build_plan(polyspec_plan_s* p) {
       return p->fail(POLYSPEC_ERR_ALIASING,
                      "order * (n_shells + 1/2) * shell_width > N; set POLYSPEC_ALLOW_ALIASING for the mod-N estimator");
   }
-  if (d.n_shells > 16 * ps::kMaxBlkHost)
-    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "the matrix-core contraction handles at most 64 shells");
+  if (d.n_shells > 16 * ps::kMaxTileBlkHost)
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "the matrix-core contraction handles at most 128 shells");
   if (d.order >= 5 && d.n_shells > ps::kMaxShells56)
     return p->fail(POLYSPEC_ERR_UNSUPPORTED, "orders 5 and 6 handle at most 32 shells");
   if ((d.flags & POLYSPEC_INPUT_HALF_SPECTRUM) && (d.N * (size_t)d.N * (d.N / 2 + 1)) == 0)
@@ -812,7 +820,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     phys = std::pow(V, p->order - 1) / std::pow((double)p->N, 3 * p->order);
   }
   std::vector<int> lookup;
-  const bool adj3 = p->order == 3, adj4 = p->order == 4 && p->nb <= ps::kAdj4MaxShells;
+  const bool adj3 = p->order == 3 && p->nb <= ps::kAdj3MaxShells, adj4 = p->order == 4 && p->nb <= ps::kAdj4MaxShells;
   if (adj3) lookup.assign((size_t)p->nb * p->nb * p->nb, -1);
   if (adj4) lookup.assign((size_t)p->nb * p->nb * p->nb * p->nb, -1);
   for (size_t c = 0; c < nc; ++c) {
@@ -849,7 +857,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   PS_TRY(upload(p, &p->bins_d, p->cl_bins));
   PS_TRY(upload(p, &p->fnorm_d, fnorm));
   PS_TRY(dev_alloc(p, &p->flag_d, 256));
-  if (p->order == 3) {
+  if (adj3) {
     PS_TRY(upload(p, &p->lookup_d, lookup));
     // for each v: which (16-shell chunk of u, 32-shell block of m) of W[m][(u, v)] can
     // be non-zero, as bits 2 uc + mb (the adjoint GEMM skips the others)
@@ -1034,10 +1042,8 @@ static polyspec_status field_maxima(polyspec_plan_t p) {
   return POLYSPEC_OK;
 }
 
-polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
-  if (!p) return POLYSPEC_ERR_INVALID_ARG;
-  if (!d_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null input");
-  PS_TRY(ensure_workspace(p));
+// a0-a2 into the carved workspace (which the caller has provided or allocated).
+static polyspec_status shells_impl(polyspec_plan_t p, const void* d_delta) {
   const int nz = p->batch * p->nb;
   hipStream_t st = p->stream;
   Geom gin = make_geom(p, 0, 0);
@@ -1063,6 +1069,13 @@ polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
   }
   p->have_fields = true;
   return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_shells(polyspec_plan_t p, const void* d_delta) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!d_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null input");
+  PS_TRY(ensure_workspace(p));
+  return shells_impl(p, d_delta);
 }
 
 // One contraction launch over the fields in D (the whole grid or one slab) and its
@@ -1163,29 +1176,31 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
   return POLYSPEC_OK;
 }
 
-polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, float* d_grad_delta) {
+polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, void* d_grad_delta) {
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
-  if (p->order != 3 && !(p->order == 4 && p->nb <= ps::kAdj4MaxShells))
-    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward is implemented for order 3, and order 4 with at most 32 shells");
-  if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM)
-    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "backward needs real-space input");
+  if (!has_adjoint(p))
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED,
+                   "backward is implemented for order 3 with at most 64 shells and order 4 with at most 32");
   if (!d_grad_out || !d_grad_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null pointer");
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_backward before polyspec_shells");
   hipStream_t st = p->stream;
   const int nz = p->batch * p->nb;
   const int ncl = (int)p->closing.size();
-  const int aprec = (p->prec == POLYSPEC_FP32) ? 0 : 1;  // FP16 mode uses the bf16 split here
+  // adjoint arithmetic: FP32, or the split of the plan's precision; a streamed plan's
+  // field scales are per slab, so its FP16 mode takes the BF16 split (no scaling needed)
+  const int aprec = p->prec == POLYSPEC_FP32 ? 0 : (p->prec == POLYSPEC_SPLIT_FP16 && !p->streamed) ? 2 : 1;
+  if (aprec == 2 && !p->absmax_valid) PS_TRY(field_maxima(p));   // precision switched after shells
   Geom gs = make_geom(p, p->nb, 1);
   const cplx<float>* tw = (const cplx<float>*)p->tw32.p;
   const bool fused = ps::adjoint_fuses_rows(p->N);   // the kernel also runs the x2 -> q2 pass
   if (p->order == 3) {
     PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
              ps::launch_adjoint_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb,
-                                        ncl, aprec, (uint4*)p->W, p->batch, st));
+                                        ncl, aprec, p->absmax, p->rowmax, (uint4*)p->W, p->batch, st));
   } else {
     PS_TIMED(p, POLYSPEC_PH_ADJ_WEIGHTS,
              ps::launch_adjoint4_weights(d_grad_out, (const double*)p->fnorm_d.p, (const int*)p->lookup_d.p, p->nb,
-                                         ncl, aprec, (uint4*)p->W, p->batch, st));
+                                         ncl, aprec, p->absmax, p->rowmax, (uint4*)p->W, p->batch, st));
   }
   // a streamed plan keeps the forward's first pass in H1 for the next slabs, so the
   // adjoint's x1 rows go to a buffer of their own
@@ -1201,12 +1216,14 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
     const long long Gk = launch_points(p);
     if (p->order == 3)
       PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
-               ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, Gk,
-                                       fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gk, p->batch, st));
+               ps::launch_adjoint_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->absmax,
+                                       p->rowmax, p->nb, Gk, fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw,
+                                       gk, p->batch, st));
     else
       PS_TIMED(p, POLYSPEC_PH_ADJ_GEMM,
-               ps::launch_adjoint4_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->nb, Gk,
-                                        fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw, gk, p->batch, st));
+               ps::launch_adjoint4_gemm(aprec, p->D, (const uint4*)p->W, (const int*)p->wmask_d.p, p->absmax,
+                                        p->rowmax, p->nb, Gk, fused ? nullptr : p->A, fused ? p->H2 : nullptr, tw,
+                                        gk, p->batch, st));
     if (!fused) PS_TIMED(p, POLYSPEC_PH_ADJ_Q3, ps::launch_r2c_q3(p->A, p->H2, tw, gk, nz, st));
     PS_TIMED(p, POLYSPEC_PH_ADJ_Q2, ps::launch_r2c_q2(p->H2, H1x, tw, gk, nz, st));
     return POLYSPEC_OK;
@@ -1224,10 +1241,17 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, f
   PS_TIMED(p, POLYSPEC_PH_ADJ_Q1, ps::launch_r2c_q1<true>(H1x, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, p->gbox, tw, gs,
                                     nz, st));
   Geom gall = make_geom(p, 0, 0);
+  if (p->desc.flags & POLYSPEC_INPUT_HALF_SPECTRUM) {
+    // the gradient stays in the input's space: the half spectrum, weighted by how often
+    // the inverse real transform reads each entry
+    PS_HIP(p, ps::launch_half_spectrum_from_box(p->gbox, (cplx<float>*)d_grad_delta, gall, p->batch, st));
+    return POLYSPEC_OK;
+  }
+  float* grad_x = (float*)d_grad_delta;
   PS_TIMED(p, POLYSPEC_PH_GRAD_P1, ps::launch_c2r_p1<float, false>(p->gbox, (const int16_t*)p->shell_q.p, (const int*)p->qmax_d.p, H1x,
                                             tw, gall, p->batch, st));
   PS_TIMED(p, POLYSPEC_PH_GRAD_P2, ps::launch_c2r_p2<float>(H1x, (const int*)p->qmax_d.p, p->H2, tw, gall, p->batch, st));
-  PS_TIMED(p, POLYSPEC_PH_GRAD_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, d_grad_delta, nullptr, tw, gall, p->batch, st));
+  PS_TIMED(p, POLYSPEC_PH_GRAD_P3, ps::launch_c2r_p3(p->H2, (const int*)p->qmax_d.p, grad_x, nullptr, tw, gall, p->batch, st));
   return POLYSPEC_OK;
 }
 
@@ -1301,7 +1325,7 @@ polyspec_status polyspec_issued_flops(polyspec_plan_t p, int32_t phase, double* 
       for (int v = 0; v <= w; ++v)
         if (p->wmask_host[w * (w + 1) / 2 + v]) blocks += v / 16 + 1;
     *flops = blocks * 32.0 * 32.0 * 16.0 * 2.0 / 32.0 * terms * pts;
-  } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 3) {
+  } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 3 && has_adjoint(p)) {
     // per partner shell v: the 32-row blocks of m with a weight, each times the
     // 16-shell chunks of u <= v, as 32 x 32 x 16 products per 32 grid points
     double blocks = 0.0;

@@ -1,4 +1,5 @@
 // Small utility kernels.
+
 #include "kernels.h"
 
 namespace ps {
