@@ -45,7 +45,8 @@ def parse():
 def kernel_source_hash() -> str:
     """Hash of the sources of the matrix-core kernels (the contraction and the adjoint)."""
     h = hashlib.sha256()
-    for f in ("contract.hip", "common.h", "kernels.h"):
+    for f in ("contract_tiles.h", "contract_tiles_lo.hip", "contract_tiles_hi.hip", "contract_j3.hip",
+              "adjoint.hip", "mfma_ops.h", "common.h", "kernels.h"):
         with open(os.path.join(ROOT, "paper_1904_11055_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -132,10 +133,11 @@ def cpu_baseline(delta32, w, n_closing, planes: int):
         "unit": "bin-triplets*gridpts/s",
         "cores": cores,
         "kind": "oracle",
+        "extrapolated": True,
         "sample": (f"FP64 oracle: one {N}^3 rfftn ({t_r2c:.2f} s) and irfftn ({t_c2r:.2f} s) scaled x{nb + 1} "
                    f"each; product sums over all {len(tuples)} candidate triplets and the adjoint pair "
                    f"GEMM on {planes} of {N} x0-planes ({t_ctr:.2f} s + {t_adj:.2f} s) scaled x{scale:g}; "
-                   f"estimated step {t_step:.1f} s"),
+                   f"estimated (extrapolated) step {t_step:.1f} s"),
     }
 
 
@@ -253,6 +255,10 @@ def main():
         dominant, other = (adj_roof, ctr_roof) if adj_ms >= ctr_ms else (ctr_roof, adj_roof)
     else:
         n_w, dominant, other = None, ctr_roof, None
+    # the adjoint runs the split of the plan's precision, except that a streamed plan's FP16
+    # mode takes the BF16 split (its field scales are per slab)
+    bwd_prec = ("bf16" if (streamed and args.precision == "fp16") else args.precision) if has_backward else None
+    dtype_label = args.precision if bwd_prec in (None, args.precision) else f"{args.precision} fwd / {bwd_prec} bwd"
     names = {3: ("bispectrum", "bin-triplets"), 4: ("trispectrum", "bin-quadruples"),
              5: ("quadspectrum", "bin-quintuples"), 6: ("pentaspectrum", "bin-sextuples")}[order]
     out = {
@@ -266,7 +272,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.precision, "data": "synthetic",
+        "dtype": dtype_label, "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "order": order, "n_shells": nb, "shell_width": width,
                    "batch": batch, "field": w["field"], "seeds": w["seeds"], "n_closing": plan.n_closing,
                    "precision": args.precision, "parallelism": "none (1 GPU)"},

@@ -27,3 +27,19 @@ def gpu():
         pytest.skip("no GPU visible")
     import torch
     return torch.device("cuda:0")
+
+
+def record_error(config: str, precision: str, **metrics) -> None:
+    """Appends one JSON line of measured errors to $POLYSPEC_ERROR_LOG (if set) and prints it."""
+    import json
+    rec = {"config": config, "precision": precision}
+    rec.update({k: (float(v) if hasattr(v, "__float__") else v) for k, v in metrics.items()})
+    line = json.dumps(rec)
+    print(f"[errors] {line}", file=sys.stderr, flush=True)
+    path = os.environ.get("POLYSPEC_ERROR_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(line + "\n")
+
+
+PRECISION_NAMES = {0: "fp32", 1: "split_bf16", 2: "split_fp16"}

@@ -40,7 +40,7 @@ def test_status_strings():
     (dict(box_length=-1.0), 1), (dict(flags=1 << 10), 1),
     (dict(n_shells=40), 1),                      # outer edge beyond Nyquist at N = 64
     (dict(n_shells=21), 2),                      # 3 * 21.5 > 64: aliasing without the flag
-    (dict(N=512, n_shells=80, shell_width=1.0), 7),  # more shells than the tile kernels hold
+    (dict(N=512, n_shells=130, shell_width=1.0), 7),  # more shells than the tile kernels hold (128)
     (dict(order=5, N=256, n_shells=40), 7),      # orders 5 and 6 hold at most 32 shells
     (dict(order=6, n_shells=16), 2),             # 6 * 16.5 > 64
 ])
