@@ -127,6 +127,23 @@ polyspec_status polyspec_contract(polyspec_plan_t plan, double* d_out, double* d
  * product runs in float32 for POLYSPEC_FP32 and in split precision otherwise. */
 polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out, void* d_grad_delta);
 
+/* polyspec_shells followed by polyspec_contract, allocating nothing: for callers that
+ * cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid it).  The workspace is the library's static scratch, a
+ * file-scope device array of POLYSPEC_STATIC_SCRATCH_BYTES held on each GPU the library
+ * runs on until the process ends (its address is looked up when a plan is made).  Plans
+ * whose workspace (polyspec_workspace_size) is larger are refused with
+ * POLYSPEC_ERR_UNSUPPORTED; the call must run with the plan's device current
+ * (POLYSPEC_ERR_INVALID_ARG otherwise).  Inputs and outputs are as for polyspec_shells
+ * and polyspec_contract.  The plan's own workspace and the shell fields kept in it are
+ * left as they were, so polyspec_backward still refers to the last polyspec_shells call.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one GPU (two
+ * streams, two host threads) race and must be serialised by the caller.  Event timing
+ * (polyspec_profile) does not cover this call. */
+#define POLYSPEC_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+polyspec_status polyspec_forward_static(polyspec_plan_t plan, const void* d_delta, double* d_out,
+                                        double* d_raw_sums);
+
 /* Bytes of device workspace the plan needs for shells, contract and backward. */
 polyspec_status polyspec_workspace_size(polyspec_plan_t plan, size_t* bytes);
 

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "PolyspecError", "Plan", "polyspectrum", "load_library",
     "FP32", "SPLIT_BF16", "SPLIT_FP16", "INPUT_HALF_SPECTRUM", "ALLOW_ALIASING", "NAN_GUARD", "STREAM_SLABS",
-    "polyspec_plan", "polyspec_shells", "polyspec_contract", "polyspec_backward",
+    "polyspec_plan", "polyspec_shells", "polyspec_contract", "polyspec_backward", "polyspec_forward_static",
     "polyspec_workspace_size", "polyspec_set_workspace", "polyspec_set_precision",
     "polyspec_set_slab_planes", "polyspec_slab_planes",
     "polyspec_tuples", "polyspec_candidates", "polyspec_fields", "polyspec_destroy",
@@ -30,6 +30,7 @@ __all__ = [
 ]
 
 FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2
+STATIC_SCRATCH_BYTES = 128 << 20   # POLYSPEC_STATIC_SCRATCH_BYTES
 INPUT_HALF_SPECTRUM, ALLOW_ALIASING, NAN_GUARD, STREAM_SLABS = 1, 2, 8, 16
 
 STATUS = {0: "POLYSPEC_OK", 1: "POLYSPEC_ERR_INVALID_ARG", 2: "POLYSPEC_ERR_ALIASING",
@@ -72,6 +73,7 @@ def load_library(path: str = LIB_PATH):
         "polyspec_plan": (ctypes.c_int, [D(polyspec_desc), V, D(P)]),
         "polyspec_shells": (ctypes.c_int, [P, V]),
         "polyspec_contract": (ctypes.c_int, [P, V, V]),
+        "polyspec_forward_static": (ctypes.c_int, [P, V, V, V]),
         "polyspec_backward": (ctypes.c_int, [P, V, V]),
         "polyspec_workspace_size": (ctypes.c_int, [P, D(ctypes.c_size_t)]),
         "polyspec_set_workspace": (ctypes.c_int, [P, V, ctypes.c_size_t]),
@@ -129,6 +131,12 @@ def polyspec_contract(plan, d_out_ptr: int, d_raw_ptr: int | None = None):
     _check(load_library().polyspec_contract(plan, ctypes.c_void_p(d_out_ptr),
                                             ctypes.c_void_p(d_raw_ptr) if d_raw_ptr else None),
            "polyspec_contract", plan)
+
+
+def polyspec_forward_static(plan, d_delta_ptr: int, d_out_ptr: int, d_raw_ptr: int | None = None):
+    _check(load_library().polyspec_forward_static(plan, ctypes.c_void_p(d_delta_ptr), ctypes.c_void_p(d_out_ptr),
+                                                  ctypes.c_void_p(d_raw_ptr) if d_raw_ptr else None),
+           "polyspec_forward_static", plan)
 
 
 def polyspec_backward(plan, d_grad_out_ptr: int, d_grad_delta_ptr: int):

@@ -129,6 +129,11 @@ hipError_t launch_adjoint4_gemm(int prec, const float* D, const uint4* W, const 
                                 cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
 
 // util.hip
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;   // polyspec_forward_static's workspace
+constexpr int kMaxDevices = 64;
+// Device address of this device's static scratch (looked up once per device, with that
+// device current).
+hipError_t static_scratch_address(int device, void** ptr);
 hipError_t launch_fill_u32(void* dst, unsigned value, size_t n_words, hipStream_t st);
 hipError_t launch_fields_absmax(const float* x, long long G, int nz, unsigned* part, int spread, hipStream_t st);
 

@@ -69,6 +69,9 @@ struct polyspec_plan_s {
   polyspec_desc desc{};
   hipStream_t stream = nullptr;
   std::string last_error;
+  int device = -1;                 // current device when the plan was made
+  void* static_scratch = nullptr;  // that device's static scratch (polyspec_forward_static)
+  hipError_t static_scratch_status = hipSuccess;
 
   int N = 0, order = 0, nb = 0, batch = 0, prec = 0;
   int Kc = 0, B0 = 0, B2 = 0, n_blk = 0;
@@ -947,6 +950,13 @@ polyspec_status polyspec_plan(const polyspec_desc* desc, void* stream, polyspec_
   }
   p->desc = *desc;
   p->stream = (hipStream_t)stream;
+  // the static scratch of this device, looked up once per device with it current
+  if (hipGetDevice(&p->device) == hipSuccess) {
+    p->static_scratch_status = ps::static_scratch_address(p->device, &p->static_scratch);
+  } else {
+    (void)hipGetLastError();
+    p->static_scratch_status = hipErrorInvalidDevice;
+  }
   polyspec_status st;
   try {
     st = build_plan(p);
@@ -1174,6 +1184,61 @@ polyspec_status polyspec_contract(polyspec_plan_t p, double* d_out, double* d_ra
     if (flag) return p->fail(POLYSPEC_ERR_DEVICE, "non-finite polyspectrum value");
   }
   return POLYSPEC_OK;
+}
+
+// The workspace pointers carved from the plan's workspace, and the state that refers to
+// them: saved and restored around a call that runs on the static scratch instead.
+namespace {
+struct CarvedState {
+  char* ws;
+  size_t ws_size;
+  cplx<float>*box, *gbox, *H1, *H1a, *H2;
+  float *D, *A, *partials, *W;
+  double* red;
+  unsigned *absmax, *absmax_part;
+  unsigned long long* rowmax;
+  bool have_fields, absmax_valid, prof;
+};
+CarvedState save_carved(const polyspec_plan_s* p) {
+  return {p->ws, p->ws_size, p->box, p->gbox, p->H1, p->H1a, p->H2, p->D, p->A, p->partials, p->W,
+          p->red, p->absmax, p->absmax_part, p->rowmax, p->have_fields, p->absmax_valid, p->prof};
+}
+void restore_carved(polyspec_plan_s* p, const CarvedState& c) {
+  p->ws = c.ws; p->ws_size = c.ws_size; p->box = c.box; p->gbox = c.gbox; p->H1 = c.H1; p->H1a = c.H1a;
+  p->H2 = c.H2; p->D = c.D; p->A = c.A; p->partials = c.partials; p->W = c.W; p->red = c.red;
+  p->absmax = c.absmax; p->absmax_part = c.absmax_part; p->rowmax = c.rowmax;
+  p->have_fields = c.have_fields; p->absmax_valid = c.absmax_valid; p->prof = c.prof;
+}
+}  // namespace
+
+static_assert(POLYSPEC_STATIC_SCRATCH_BYTES == ps::kStaticScratchBytes, "header and library agree on the scratch size");
+
+polyspec_status polyspec_forward_static(polyspec_plan_t p, const void* d_delta, double* d_out, double* d_raw_sums) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!d_delta || !d_out) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null input or output");
+  const size_t need = layout_of(p).total;
+  if (need > ps::kStaticScratchBytes)
+    return p->fail(POLYSPEC_ERR_UNSUPPORTED, "the plan needs " + std::to_string(need) +
+                                                 " bytes of workspace; the static scratch holds " +
+                                                 std::to_string(ps::kStaticScratchBytes));
+  if (p->static_scratch_status != hipSuccess || p->static_scratch == nullptr)
+    return p->fail(POLYSPEC_ERR_DEVICE, std::string("static scratch unavailable: ") +
+                                            hipGetErrorString(p->static_scratch_status));
+  int cur = -1;
+  PS_HIP(p, hipGetDevice(&cur));
+  if (cur != p->device) return p->fail(POLYSPEC_ERR_INVALID_ARG, "the plan's device is not the current device");
+  // run shells + contract on the static scratch; the plan's own workspace (if any) and
+  // the fields kept in it are untouched.  Event timing is off for the call (it would
+  // create events).
+  const CarvedState saved = save_carved(p);
+  p->ws = (char*)p->static_scratch;
+  p->ws_size = ps::kStaticScratchBytes;
+  carve(p, p->ws);
+  p->prof = false;
+  polyspec_status st = shells_impl(p, d_delta);
+  if (st == POLYSPEC_OK) st = polyspec_contract(p, d_out, d_raw_sums);
+  restore_carved(p, saved);
+  return st;
 }
 
 polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, void* d_grad_delta) {

@@ -1,8 +1,34 @@
-// Small utility kernels.
+// Small utility kernels, and the library's static device scratch.
+#include <mutex>
 
 #include "kernels.h"
 
 namespace ps {
+
+// Workspace of polyspec_forward_static (for callers that cannot allocate): a
+// file-scope device array, one copy per GPU, held until the process ends.  Host code
+// never passes this name to a kernel (on the host it is only a stand-in); it uses
+// the device address that static_scratch_address() looks up once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(int device, void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[device] == nullptr) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the lookup runs with `device` current
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = a;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 // Fills n_words 32-bit words with value (a kernel rather than hipMemsetAsync so
 // that the work stays an ordinary kernel node when a caller captures the stream).
