@@ -59,9 +59,13 @@ constexpr size_t adj_lds_bytes() {
   const size_t stage = (size_t)2 * kAdjStageWords * sizeof(uint4);
   return adj_fft_lds_bytes<NF>() > stage ? adj_fft_lds_bytes<NF>() : stage;
 }
+constexpr int kAdj4StageItems = 8;                                    // items (w, v) per order-4 stage
+constexpr int kAdj4StageWords = kAdj4StageItems * kAdj4WordsPerItem;
+constexpr int kAdj4Piece = kAdj4StageWords / kAdjThreads;            // words per thread per stage
+static_assert(kAdj4Piece * kAdjThreads == kAdj4StageWords, "an order-4 stage is copied in equal pieces");
 template <int NF>
 constexpr size_t adj4_lds_bytes() {
-  const size_t stage = (size_t)kAdj4MaxShells * kAdj4WordsPerItem * sizeof(uint4);   // the items of one w
+  const size_t stage = (size_t)2 * kAdj4StageWords * sizeof(uint4);   // double buffered
   return adj_fft_lds_bytes<NF>() > stage ? adj_fft_lds_bytes<NF>() : stage;
 }
 
@@ -291,19 +295,22 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
 
   const uint4* Wb = W + (size_t)b * n_shells * kAdjWPerV;
   const int n_stages = (n_shells + kAdjVG - 1) / kAdjVG;
-  uint4 wp[kAdjPiece];
-  // piece q of stage s: words (q kAdjPiece + k) kAdjThreads + tid of the stage
+  u32x4 wp[kAdjPiece];   // a native vector: an array of uint4 here ends up in scratch memory
+  // piece q of stage s: words (q kAdjPiece + k) kAdjThreads + tid of the stage.  Words of
+  // v >= n_shells (a last, partial stage) are never read from LDS, so their loads only
+  // need to stay in bounds: they reread the batch's first words.  No branch around the
+  // load: a guarded load makes the compiler wait for it on the spot.
   auto w_load = [&](int s, int q) {
 #pragma unroll
     for (int k = 0; k < kAdjPiece; ++k) {
       const int i = (q * kAdjPiece + k) * kAdjThreads + tid;
       const int v = s * kAdjVG + i / kAdjWPerV;
-      wp[k] = v < n_shells ? Wb[(size_t)s * kAdjStageWords + i] : make_uint4(0, 0, 0, 0);
+      wp[k] = *reinterpret_cast<const u32x4*>(Wb + (v < n_shells ? (size_t)s * kAdjStageWords + i : (size_t)i));
     }
   };
   auto w_store = [&](int buf, int q) {
 #pragma unroll
-    for (int k = 0; k < kAdjPiece; ++k) wst[buf][(q * kAdjPiece + k) * kAdjThreads + tid] = wp[k];
+    for (int k = 0; k < kAdjPiece; ++k) *reinterpret_cast<u32x4*>(&wst[buf][(q * kAdjPiece + k) * kAdjThreads + tid]) = wp[k];
   };
   for (int q = 0; q < kAdjVG; ++q) {
     w_load(0, q);
@@ -365,9 +372,12 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
 }
 
 // Order 4 (at most 32 shells, one 32-row block of m).  Items (w, v <= w) in order of w;
-// for each w the weights of its items are staged in LDS, and for each item the B
-// operand is d_u (chunk uc <= v / 16) times the scalar d_v d_w (FP16: times 2^-7, so
-// that the triple products of scaled fields stay below 2^14).
+// for each item the B operand is d_u (chunk uc <= v / 16) times the scalar d_v d_w
+// (FP16: times 2^-7, so that the triple products of scaled fields stay below 2^14).
+// The weights pass through LDS in stages of kAdj4StageItems items of one w (v in
+// [8 c, 8 c + 8)), double buffered: the next stage is loaded into registers while one
+// is in use, then stored, with one barrier per stage.  d_w and the item masks of the
+// next w are likewise loaded a w ahead.
 template <int PREC, int NF>
 __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __restrict__ D,
                                                               const uint4* __restrict__ W,
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
                                                               cplx<float>* __restrict__ H2,
                                                               const cplx<float>* __restrict__ tw, Geom g) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[adj4_lds_bytes<NF>()];
-  uint4* wst = reinterpret_cast<uint4*>(lds);
+  auto wst = reinterpret_cast<uint4(*)[kAdj4StageWords]>(lds);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -388,6 +398,7 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
   const float* Db = D + (size_t)b * n_shells * G;
   const int n_items = n_shells * (n_shells + 1) / 2;
   const uint4* Wb = W + (size_t)b * n_items * kAdj4WordsPerItem;
+  const int* Ib = imask;   // one mask per item, shared by the batch
 
   AdjFields<PREC, 2> f;
   adj_load_fields<PREC, 2>(f, Db, G, xw, hh, n_shells, absmax, b);
@@ -399,16 +410,38 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[pb][mb][i] = 0.f;
 
+  // stage (w, c): items w (w + 1) / 2 + 8 c + k, k < 8.  Items past w are never read
+  // from LDS; their loads only stay in bounds (they reread the first item).
+  u32x4 wp[kAdj4Piece];
+  auto s_load = [&](int w, int c) {
+    const size_t base = (size_t)(w * (w + 1) / 2 + kAdj4StageItems * c) * kAdj4WordsPerItem;
+#pragma unroll
+    for (int k = 0; k < kAdj4Piece; ++k) {
+      const int i = k * kAdjThreads + tid;
+      const bool real = kAdj4StageItems * c + i / kAdj4WordsPerItem <= w;
+      wp[k] = *reinterpret_cast<const u32x4*>(Wb + (real ? base + i : (size_t)(i % kAdj4WordsPerItem)));
+    }
+  };
+  auto s_store = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < kAdj4Piece; ++k) *reinterpret_cast<u32x4*>(&wst[buf][k * kAdjThreads + tid]) = wp[k];
+  };
+  s_load(0, 0);
+  s_store(0);
+  // d_w at the lane's points and the masks of the items (w, v = lane), a w ahead
+  float dw_next[kAdjPB];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb) dw_next[pb] = Db[xw + 32 * pb];
+  int mask_next = lane == 0 ? Ib[0] : 0;
+  __syncthreads();
+
+  int buf = 0;
   for (int w = 0; w < n_shells; ++w) {
-    const int it0 = w * (w + 1) / 2;
-    __syncthreads();                              // the previous w's stage is consumed
-    for (int i = tid; i < (w + 1) * kAdj4WordsPerItem; i += kAdjThreads) wst[i] = Wb[(size_t)it0 * kAdj4WordsPerItem + i];
-    // d_w at the lane's points (FP16: scaled and split like the register fields)
     unsigned sw_[kAdjPB];
 #pragma unroll
     for (int pb = 0; pb < kAdjPB; ++pb) {
-      const float x = Db[(size_t)w * G + xw + 32 * pb];
-      if constexpr (PREC == kFP16) {
+      const float x = dw_next[pb];
+      if constexpr (PREC == kFP16) {   // scaled and split like the register fields
         const float y = ldexpf(x, shell_scale_exp(absmax, b * n_shells + w));
         const _Float16 h = (_Float16)y;
         const _Float16 l = (_Float16)(y - (float)h);
@@ -417,17 +450,31 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
         sw_[pb] = __float_as_uint(x);
       }
     }
-    const int my_mask = lane <= w ? imask[it0 + lane] : 0;   // items (w, v = lane)
-    __syncthreads();
-    static_for<2>([&](auto vcc) {
-      constexpr int vc = decltype(vcc)::value;
-      static_for<16>([&](auto vvc) {
-        constexpr int vv = decltype(vvc)::value;
-        const int v = 16 * vc + vv;
+    const int my_mask = mask_next;
+    if (w + 1 < n_shells) {
+#pragma unroll
+      for (int pb = 0; pb < kAdjPB; ++pb) dw_next[pb] = Db[(size_t)(w + 1) * G + xw + 32 * pb];
+      const int it1 = (w + 1) * (w + 2) / 2;
+      mask_next = lane <= w + 1 ? Ib[it1 + lane] : 0;
+    }
+    static_for<kAdj4MaxShells / kAdj4StageItems>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (kAdj4StageItems * c > w) return;
+      int nw = w, nc = c + 1;                       // the stage after this one
+      if (kAdj4StageItems * nc > w) {
+        nw = w + 1;
+        nc = 0;
+      }
+      const bool more = nw < n_shells;
+      if (more) s_load(nw, nc);
+      static_for<kAdj4StageItems>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int v = kAdj4StageItems * c + k;
+        constexpr int vc = v / 16, vv = v % 16;
         if (v > w) return;
         const int mask = __builtin_amdgcn_readlane(my_mask, v);   // bit uc
         if (!mask) return;
-        const uint4* wv = wst + v * kAdj4WordsPerItem;
+        const uint4* wv = wst[buf] + k * kAdj4WordsPerItem;
         unsigned s[kAdjPB];
 #pragma unroll
         for (int pb = 0; pb < kAdjPB; ++pb) {
@@ -445,10 +492,12 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
           }
         });
       });
+      if (more) s_store(buf ^ 1);
+      __syncthreads();                              // the next stage is complete; this one is free
+      buf ^= 1;
     });
   }
   adj_unscale<PREC>(acc, rowmax, b, hh);
-  __syncthreads();
   adjoint_epilogue<NF>(acc, lds, lane, wave, hh, col, b, xw, n_shells, G, A, H2, tw, g);
 }
 
