@@ -166,10 +166,11 @@ def main():
     order = w["order"]
     if order not in (3, 4, 5, 6):
         raise SystemExit("the benchmark step needs an order-3 to order-6 workload")
-    # orders 3 and 4 have the adjoint: a step is forward + backward; orders 5 and 6 forward only
+    # orders 3 (up to 64 shells) and 4 (up to 32) have the adjoint: a step is forward +
+    # backward; otherwise forward only
     streamed = bool(w.get("stream"))
-    has_backward = order in (3, 4)
     N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
+    has_backward = (order == 3 and nb <= 64) or (order == 4 and nb <= 32)
     prec = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}[args.precision]
     dev = torch.device("cuda:0")
     flags = ps.STREAM_SLABS if streamed else 0
@@ -239,7 +240,7 @@ def main():
     # for the contraction; 2 per (adjoint weight x point) + 1 per (pair x point) for the
     # adjoint product, whatever the tiles the kernels actually issue
     # the FP16 split of an order-3 plan runs the shell-block aligned kernel
-    ctr_kernel = "contract_j3" if (args.precision == "fp16" and order == 3) else "contract_tiles"
+    ctr_kernel = "contract_j3" if (args.precision == "fp16" and order == 3 and nb <= 64) else "contract_tiles"
     # algorithmic flops: 2 per (closing tuple x point), plus the row products formed once
     # per point: 1 per pair (orders 3 to 5) and 2 per triple (orders 5 and 6)
     row_flops = (n_pairs if order <= 5 else 0) + (2 * n_triples if order >= 5 else 0)

@@ -134,6 +134,11 @@ WORKLOADS = {
     "bispec_1024_streamed": dict(N=1024, order=3, n_shells=64, width=1.0, batch=1,
                                  field="lognormal", seeds=[5], spectrum_of="bispec_512_lognormal",
                                  stream=True),
+    # 128 unit shells on the same 1024^3 input (alias-free: 3 x 128.5 <= 1024); the
+    # contraction stages eight 16-shell blocks; forward only (the adjoint holds 64 shells)
+    "bispec_1024_streamed_128": dict(N=1024, order=3, n_shells=128, width=1.0, batch=1,
+                                     field="lognormal", seeds=[5], spectrum_of="bispec_512_lognormal",
+                                     stream=True),
 }
 
 

@@ -618,3 +618,35 @@ def test_more_than_64_shells(gpu, precision, tol):
     assert e.value.status == 7
     plan.close()
 
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
+def test_more_than_64_shells_streamed(gpu, precision, tol):
+    """The 80-shell plan above run slab by slab (16 slabs of 8 planes): every closing triplet
+    against the oracle, and against the resident plan."""
+    import torch
+    ps = _ps()
+    N, nb, width = 128, 80, 0.5
+    key = ("more_than_64",)
+    if key not in _CACHE:
+        delta = fieldgen.lognormal_field(N, 93).astype(np.float32)
+        ref = O.polyspectrum(delta.astype(np.float64), 3, nb, width, return_fields=True)
+        ref["A"] = O.product_sums(np.abs(ref["fields"]), ref["tuples"]) / (float(N) ** 3 * ref["counts"])
+        del ref["fields"]
+        _CACHE[key] = (delta, ref)
+    delta, ref = _CACHE[key]
+    x = torch.from_numpy(delta)[None].to("cuda:0")
+    plan = ps.Plan(N, 3, nb, width, precision=precision, flags=ps.STREAM_SLABS, slab_planes=8, device="cuda:0")
+    assert plan.slab_planes == 8
+    plan.shells(x)
+    B = plan.contract().cpu().numpy()
+    assert np.array_equal(plan.counts, ref["counts"])
+    from conftest import PRECISION_NAMES, record_error
+    scaled = float(np.max(np.abs(B[0] - ref["B"]) / ref["A"]))
+    record_error("128^3 bispectrum, 80 shells of width 1/2, streamed (16 slabs)", PRECISION_NAMES[precision],
+                 n_tuples=len(ref["B"]), rel_l2=_rel(B[0], ref["B"]), max_scaled=scaled)
+    assert _rel(B[0], ref["B"]) < tol
+    assert scaled < tol
+    plan.close()
+    _, Br, _ = _run(delta, 3, nb, width, precision=precision)
+    assert _rel(B[0], Br[0]) < tol
+
