@@ -46,7 +46,8 @@ def kernel_source_hash() -> str:
     """Hash of the sources of the matrix-core kernels (the contraction and the adjoint)."""
     h = hashlib.sha256()
     for f in ("contract_tiles.h", "contract_tiles_lo.hip", "contract_tiles_hi.hip", "contract_j3.hip",
-              "adjoint.hip", "mfma_ops.h", "common.h", "kernels.h"):
+              "adjoint.h", "adjoint.hip", "adjoint_fp32.hip", "adjoint_bf16.hip", "adjoint_fp16.hip",
+              "mfma_ops.h", "fft_core.h", "common.h", "kernels.h"):
         with open(os.path.join(ROOT, "paper_1904_11055_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -249,10 +250,11 @@ def main():
                         load_traffic(ctr_kernel, args.workload, args.precision))
     if has_backward:
         n_w = adjoint_weight_entries(plan.tuples)
-        adj_roof = roofline("adjoint_gemm" if order == 3 else "adjoint4_gemm", adj_ms,
+        adj_kernel = "adjoint_gemm" if order == 3 else "adjoint4_gemm"
+        adj_roof = roofline(adj_kernel, adj_ms,
                             (2.0 * n_w + n_rests * (order - 2)) * G * batch / launches,
                             ps.polyspec_issued_flops(plan.handle, "adj_gemm") / launches, peak,
-                            load_traffic("adjoint_gemm", args.workload, args.precision))
+                            load_traffic(adj_kernel, args.workload, args.precision))
         dominant, other = (adj_roof, ctr_roof) if adj_ms >= ctr_ms else (ctr_roof, adj_roof)
     else:
         n_w, dominant, other = None, ctr_roof, None
