@@ -244,6 +244,19 @@ __device__ __forceinline__ void adj_mma(f32x16& acc, const Operand<PREC>& a, con
   }
 }
 
+// As adj_mma, into a fresh accumulator (C = 0).
+template <int PREC>
+__device__ __forceinline__ void adj_mma_first(f32x16& acc, const Operand<PREC>& a, const Operand<PREC>& b) {
+  if constexpr (PREC == kFP16) {
+    const f32x16 z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.hi, b.hi, z, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.hi, b.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.lo, b.hi, acc, 0, 0, 0);
+  } else {
+    mma32_first<PREC>(acc, a, b);
+  }
+}
+
 // FP16: multiply every accumulated row by 2^-e_m (the weight row's scale).
 template <int PREC>
 __device__ __forceinline__ void adj_unscale(f32x16 (&acc)[kAdjPB][kAdjMaxMb], const unsigned long long* rowmax,
@@ -372,12 +385,15 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
 }
 
 // Order 4 (at most 32 shells, one 32-row block of m).  Items (w, v <= w) in order of w;
-// for each item the B operand is d_u (chunk uc <= v / 16) times the scalar d_v d_w
-// (FP16: times 2^-7, so that the triple products of scaled fields stay below 2^14).
-// The weights pass through LDS in stages of kAdj4StageItems items of one w (v in
-// [8 c, 8 c + 8)), double buffered: the next stage is loaded into registers while one
-// is in use, then stored, with one barrier per stage.  d_w and the item masks of the
-// next w are likewise loaded a w ahead.
+// for each item Y = sum over the chunks uc <= v / 16 of W4_(v,w) d_u runs on the matrix
+// cores with the fields themselves as the B operand, and a_m += d_v d_w Y on the VALU,
+// one float32 multiply-add per accumulator element (FP16: the scaled scalar times 2^-7,
+// the shift that the weights' row exponents carry).  Forming d_u d_v d_w for every item
+// and chunk instead cost more VALU instructions than the MFMAs could hide.  The weights
+// pass through LDS in stages of kAdj4StageItems items of one w (v in [8 c, 8 c + 8)),
+// double buffered: the next stage is loaded into registers while one is in use, then
+// stored, with one barrier per stage.  d_w and the item masks of the next w are likewise
+// loaded a w ahead.
 template <int PREC, int NF>
 __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __restrict__ D,
                                                               const uint4* __restrict__ W,
@@ -402,6 +418,15 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
 
   AdjFields<PREC, 2> f;
   adj_load_fields<PREC, 2>(f, Db, G, xw, hh, n_shells, absmax, b);
+  // the fields as B operands (FP16: the split operands themselves)
+  Operand<PREC> fop[kAdjPB][2];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+    for (int uc = 0; uc < 2; ++uc) {
+      if constexpr (PREC == kFP16) fop[pb][uc] = f.H[pb][uc];
+      else fop[pb][uc] = make_operand<PREC>(f.F[pb][uc], 1.f);
+    }
   f32x16 acc[kAdjPB][kAdjMaxMb];
 #pragma unroll
   for (int pb = 0; pb < kAdjPB; ++pb)
@@ -437,18 +462,11 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
 
   int buf = 0;
   for (int w = 0; w < n_shells; ++w) {
-    unsigned sw_[kAdjPB];
+    float dw[kAdjPB];   // FP16: d_w scaled like the register fields, times 2^-7
 #pragma unroll
     for (int pb = 0; pb < kAdjPB; ++pb) {
-      const float x = dw_next[pb];
-      if constexpr (PREC == kFP16) {   // scaled and split like the register fields
-        const float y = ldexpf(x, shell_scale_exp(absmax, b * n_shells + w));
-        const _Float16 h = (_Float16)y;
-        const _Float16 l = (_Float16)(y - (float)h);
-        sw_[pb] = (unsigned)__builtin_bit_cast(unsigned short, h) | ((unsigned)__builtin_bit_cast(unsigned short, l) << 16);
-      } else {
-        sw_[pb] = __float_as_uint(x);
-      }
+      if constexpr (PREC == kFP16) dw[pb] = ldexpf(dw_next[pb], shell_scale_exp(absmax, b * n_shells + w) - kTripleShift);
+      else dw[pb] = dw_next[pb];
     }
     const int my_mask = mask_next;
     if (w + 1 < n_shells) {
@@ -475,22 +493,29 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
         const int mask = __builtin_amdgcn_readlane(my_mask, v);   // bit uc
         if (!mask) return;
         const uint4* wv = wst[buf] + k * kAdj4WordsPerItem;
-        unsigned s[kAdjPB];
-#pragma unroll
-        for (int pb = 0; pb < kAdjPB; ++pb) {
-          const unsigned dv = adj_scalar<PREC, 2, vc, vv>(f, pb);
-          if constexpr (PREC == kFP16) s[pb] = f16_scalar_product(dv, sw_[pb], kTripleShift);
-          else s[pb] = __float_as_uint(__uint_as_float(dv) * __uint_as_float(sw_[pb]));
-        }
+        f32x16 Y[kAdjPB];
         static_for<vc + 1>([&](auto ucc) {
           constexpr int uc = decltype(ucc)::value;   // no branch per chunk (zero weights where empty)
           const Operand<PREC> Wop = op_from_words<PREC>(wv[uc * 128 + lane], wv[uc * 128 + 64 + lane]);
 #pragma unroll
           for (int pb = 0; pb < kAdjPB; ++pb) {
-            const Operand<PREC> P = adj_pair_operand<PREC, 2>(f, pb, uc, s[pb]);
-            adj_mma<PREC>(acc[pb][0], Wop, P);
+            if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
+            else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
           }
         });
+#pragma unroll
+        for (int pb = 0; pb < kAdjPB; ++pb) {
+          const unsigned dv = adj_scalar<PREC, 2, vc, vv>(f, pb);
+          float sv;
+          if constexpr (PREC == kFP16)
+            sv = (float)__builtin_bit_cast(_Float16, (unsigned short)(dv & 0xffffu)) +
+                 (float)__builtin_bit_cast(_Float16, (unsigned short)(dv >> 16));
+          else
+            sv = __uint_as_float(dv);
+          const float s = sv * dw[pb];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[pb][0][i] = fmaf(s, Y[pb][i], acc[pb][0][i]);
+        }
       });
       if (more) s_store(buf ^ 1);
       __syncthreads();                              // the next stage is complete; this one is free
