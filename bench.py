@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bispec_512_lognormal")
     ap.add_argument("--precision", default="fp16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--bwd-precision", default="auto", choices=["auto", "bf16", "fp16", "fp32"],
+                    help="the adjoint's arithmetic; auto: the BF16 split after a split-precision forward "
+                         "(the matrix cores sustain a higher rate on BF16 operands under the power limit), "
+                         "FP32 after FP32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=8, help="x0-planes in the oracle's timing sample")
@@ -172,7 +176,10 @@ def main():
     streamed = bool(w.get("stream"))
     N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
     has_backward = (order == 3 and nb <= 64) or (order == 4 and nb <= 32)
-    prec = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}[args.precision]
+    codes = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}
+    prec = codes[args.precision]
+    bwd_name = args.bwd_precision if args.bwd_precision != "auto" else ("fp32" if args.precision == "fp32" else "bf16")
+    bwd_code = codes[bwd_name]
     dev = torch.device("cuda:0")
     flags = ps.STREAM_SLABS if streamed else 0
     if w.get("spectrum_of"):
@@ -202,7 +209,14 @@ def main():
     def step():
         plan.shells(x)
         B = plan.contract()
-        return B, (plan.backward(2.0 * B) if has_backward else None)
+        if not has_backward:
+            return B, None
+        if bwd_code != prec:          # the adjoint's precision, set between the calls
+            plan.precision = bwd_code
+        g = plan.backward(2.0 * B)
+        if bwd_code != prec:
+            plan.precision = prec
+        return B, g
 
     for i in range(args.warmup):
         step()
@@ -251,16 +265,19 @@ def main():
     if has_backward:
         n_w = adjoint_weight_entries(plan.tuples)
         adj_kernel = "adjoint_gemm" if order == 3 else "adjoint4_gemm"
+        plan.precision = bwd_code         # the issued products of the adjoint's own precision
+        adj_issued = ps.polyspec_issued_flops(plan.handle, "adj_gemm")
+        plan.precision = prec
         adj_roof = roofline(adj_kernel, adj_ms,
                             (2.0 * n_w + n_rests * (order - 2)) * G * batch / launches,
-                            ps.polyspec_issued_flops(plan.handle, "adj_gemm") / launches, peak,
-                            load_traffic(adj_kernel, args.workload, args.precision))
+                            adj_issued / launches, PEAK_TFLOPS[bwd_name],
+                            load_traffic(adj_kernel, args.workload, bwd_name))
         dominant, other = (adj_roof, ctr_roof) if adj_ms >= ctr_ms else (ctr_roof, adj_roof)
     else:
         n_w, dominant, other = None, ctr_roof, None
-    # the adjoint runs the split of the plan's precision, except that a streamed plan's FP16
-    # mode takes the BF16 split (its field scales are per slab)
-    bwd_prec = ("bf16" if (streamed and args.precision == "fp16") else args.precision) if has_backward else None
+    # a streamed plan's FP16 mode takes the BF16 split in the adjoint (its field scales are
+    # per slab)
+    bwd_prec = (("bf16" if (streamed and bwd_name == "fp16") else bwd_name) if has_backward else None)
     dtype_label = args.precision if bwd_prec in (None, args.precision) else f"{args.precision} fwd / {bwd_prec} bwd"
     names = {3: ("bispectrum", "bin-triplets"), 4: ("trispectrum", "bin-quadruples"),
              5: ("quadspectrum", "bin-quintuples"), 6: ("pentaspectrum", "bin-sextuples")}[order]

@@ -276,10 +276,15 @@ __device__ __forceinline__ void adj_unscale(f32x16 (&acc)[kAdjPB][kAdjMaxMb], co
 }
 
 // Order 3.  A workgroup of 8 waves owns 512 grid points (each wave two 32-point
-// column blocks) and every m.  The weight operands of kAdjVG values of v at a time are
-// staged in LDS, double buffered: while one stage is in use the next one is copied in,
-// a piece per v, with one barrier per stage.  Each weight block read from LDS feeds
-// both column blocks.  Values of v without any weight (vmask) are skipped.
+// column blocks) and every m.  For each partner v and 32-row block mb of m,
+// Y = sum over the chunks uc <= v / 16 of W_v[uc, mb] d_u runs on the matrix cores with
+// the register-held field operands as B, and a_m += d_v Y is one float32 multiply-add
+// per accumulator element (forming d_u d_v for every chunk on the VALU instead, and
+// accumulating on the matrix cores directly, measured slower).  The weight operands of
+// kAdjVG values of v at a time are staged in LDS, double buffered: while one stage is in
+// use the next one is copied in, a piece per v, with one barrier per stage.  Each weight
+// block read from LDS feeds both column blocks.  Values of v, and (v, mb) blocks,
+// without any weight (vmask: bit 2 uc + mb) are skipped.
 // MBN: 32-row blocks of m that can hold a weight (1 when n_shells <= 32, else 2).
 template <int PREC, int NF, int MBN>
 __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __restrict__ D,
@@ -302,9 +307,18 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
 
   AdjFields<PREC, 4> f;
   adj_load_fields<PREC, 4>(f, Db, G, xw, hh, n_shells, absmax, b);
+  // the fields as B operands (FP16: the split operands themselves)
+  Operand<PREC> fop[kAdjPB][4];
+#pragma unroll
+  for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+    for (int uc = 0; uc < 4; ++uc) {
+      if constexpr (PREC == kFP16) fop[pb][uc] = f.H[pb][uc];
+      else fop[pb][uc] = make_operand<PREC>(f.F[pb][uc], 1.f);
+    }
 
-  // v with any weight, as a 64-bit mask in scalar registers (one ballot of the per-v masks)
-  const unsigned long long vany = __ballot(lane < n_shells && vmask[lane] != 0);
+  // the weight-block masks of every v, one per lane (bit 2 uc + mb)
+  const int vml = lane < n_shells ? vmask[lane] : 0;
 
   const uint4* Wb = W + (size_t)b * n_shells * kAdjWPerV;
   const int n_stages = (n_shells + kAdjVG - 1) / kAdjVG;
@@ -352,27 +366,39 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
         if (vi > 0) w_store((st + 1) & 1, vi - 1);
         w_load(st + 1, vi);
       }
-      // every (uc <= vc, mb < MBN) block runs without a branch (blocks without a closing
-      // tuple hold zero weights), so that the pair formation of one block and the matrix
-      // products of the others sit in one basic block and can overlap
-      if ((vany >> v) & 1ull) {
+      const int mask = __builtin_amdgcn_readlane(vml, v);
+      if (mask != 0) {
         const uint4* wv = wst[st & 1] + vi * kAdjWPerV;
-        unsigned s[kAdjPB];
+        // d_v at the lane's points as float32 (FP16: the scaled value)
+        float dv[kAdjPB];
 #pragma unroll
-        for (int pb = 0; pb < kAdjPB; ++pb) s[pb] = adj_scalar<PREC, 4, vc, vv>(f, pb);
-        static_for<vc + 1>([&](auto ucc) {
-          constexpr int uc = decltype(ucc)::value;
-          Operand<PREC> P[kAdjPB];
+        for (int pb = 0; pb < kAdjPB; ++pb) {
+          const unsigned w = adj_scalar<PREC, 4, vc, vv>(f, pb);
+          if constexpr (PREC == kFP16)
+            dv[pb] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu)) +
+                     (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+          else
+            dv[pb] = __uint_as_float(w);
+        }
 #pragma unroll
-          for (int pb = 0; pb < kAdjPB; ++pb) P[pb] = adj_pair_operand<PREC, 4>(f, pb, uc, s[pb]);
-#pragma unroll
-          for (int mb = 0; mb < MBN; ++mb) {
+        for (int mb = 0; mb < MBN; ++mb) {
+          if (!(mask & (0x55 << mb))) continue;   // no weight in this block of m
+          f32x16 Y[kAdjPB];
+          static_for<vc + 1>([&](auto ucc) {
+            constexpr int uc = decltype(ucc)::value;
             const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
             const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
 #pragma unroll
-            for (int pb = 0; pb < kAdjPB; ++pb) adj_mma<PREC>(acc[pb][mb], Wop, P[pb]);
-          }
-        });
+            for (int pb = 0; pb < kAdjPB; ++pb) {
+              if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
+              else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+            }
+          });
+#pragma unroll
+          for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[pb][mb][i] = fmaf(dv[pb], Y[pb][i], acc[pb][mb][i]);
+        }
       }
       if (more && (vi == kAdjVG - 1)) {
         w_store((st + 1) & 1, kAdjVG - 1);
