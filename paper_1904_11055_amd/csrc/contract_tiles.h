@@ -9,9 +9,16 @@ namespace ps {
 template <int ORDER>
 constexpr int slots_for() { return ORDER == 2 ? 4 : ORDER == 3 ? kSlots : ORDER == 4 ? kSlots4 : ORDER == 5 ? kSlots56 : kSlots6; }
 
+constexpr int kMaxPairBlocks = kMaxPairBlocksHost;
+
 // MB: shell blocks of 16 staged per K-step (4: up to 64 shells; 8: up to 128, orders 2 to 4).
-template <int PREC, int ORDER, int MB>
+// PLDS (order 4, FP16): at the start of each K-step every pair block's operands (both
+// 32-point halves) are formed once, by the waves in turn, into LDS, and each slot reads
+// its A and B operands from there; otherwise each slot forms them itself from the staged
+// shell words, which costs more VALU instructions than its three MFMAs can hide.
+template <int PREC, int ORDER, int MB, bool PLDS = false>
 __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
+  static_assert(!PLDS || (ORDER == 4 && PREC == kFP16), "shared pair operands: order 4, split FP16");
   // FP16 up to order 4 forms pair products from the operand words alone; the other
   // precisions, and every precision at orders 5 and 6, form their row products from
   // float32 rows staged in `stage`
@@ -26,10 +33,13 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
   __shared__ uint4 opHi[2][2][MB + 1][64];
   __shared__ uint4 opLo[2][2][MB + 1][64];
   __shared__ float lds_scale[MB * 16 + 1];
+  // [32-point half][pair block][hi, lo][lane]
+  __shared__ uint4 pairOp[PLDS ? 2 * kMaxPairBlocks * 2 * 64 : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int my_slot = op_slot(lane);
+  auto pair_word = [&](int h, int pb, int part) -> uint4& { return pairOp[((h * kMaxPairBlocks + pb) * 2 + part) * 64 + lane]; };
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4;   // which 8-point group of a K-step
   const int row = lane & 15;
@@ -120,10 +130,25 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
 #pragma unroll
   for (int i = 0; i < (NS + 3) / 4; ++i) un[i] = __builtin_amdgcn_readfirstlane(uni[i]);
   int lv[NLW];
-  if (ORDER >= 3) {
+  if (ORDER >= 3 && !PLDS) {
     const int* lw = p.slot_lane + (((size_t)group * kCtrWaves + wave) * 16 + row) * kSlotsMax;
 #pragma unroll
     for (int i = 0; i < NLW; ++i) lv[i] = lw[i];
+  }
+  // PLDS: the slots' pair blocks (uniform) and the pairs this lane forms each K-step
+  constexpr int kForm = PLDS ? (2 * kMaxPairBlocks + kCtrWaves - 1) / kCtrWaves : 1;
+  int blk[PLDS ? NS : 1];
+  int fuv[kForm];
+  if constexpr (PLDS) {
+    const int* bw = p.slot_blk + ((size_t)group * kCtrWaves + wave) * kSlotsMax;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) blk[s] = __builtin_amdgcn_readfirstlane(bw[s]);
+#pragma unroll
+    for (int f = 0; f < kForm; ++f) {
+      const int t = wave + f * kCtrWaves;           // (pair block t / 2, half t % 2)
+      const int w = t < 2 * p.n_pair_blocks ? p.pair_uv[16 * (t >> 1) + row] : 0;
+      fuv[f] = (w & 0xff) | (((w >> 16) & 0xff) << 8);
+    }
   }
   for (int ks = 0; ks < p.ksteps; ++ks) {
     const int cur = ks & 1;
@@ -134,6 +159,18 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
           pre[q] = *reinterpret_cast<const float4*>(Db + (size_t)st_row[q] * p.G + x_base + (ks + 1) * kKStep + st_col[q]);
     }
     const float* S = stage[cur];
+    if constexpr (PLDS) {
+#pragma unroll
+      for (int f = 0; f < kForm; ++f) {
+        const int t = wave + f * kCtrWaves;
+        if (t < 2 * p.n_pair_blocks) {
+          const Operand<kFP16> o = form_pair_f16(opHi[cur][t & 1], opLo[cur][t & 1], fuv[f], lane);
+          pair_word(t & 1, t >> 1, 0) = __builtin_bit_cast(uint4, o.hi);
+          pair_word(t & 1, t >> 1, 1) = __builtin_bit_cast(uint4, o.lo);
+        }
+      }
+      __syncthreads();                              // every pair operand of the K-step is in LDS
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       Operand<PREC> A;
@@ -141,6 +178,16 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
       for (int s = 0; s < NS; ++s) {
         const int info = (un[s / 4] >> (8 * (s % 4))) & 0xff;
         if (info & 0x80) break;
+        if constexpr (PLDS) {
+          if (info & 0x40) {
+            const int a = blk[s] & 0xffff;
+            A = op_from_words<PREC>(pair_word(h, a, 0), pair_word(h, a, 1));
+          }
+          const int bb = blk[s] >> 16;
+          const Operand<PREC> Bp = op_from_words<PREC>(pair_word(h, bb, 0), pair_word(h, bb, 1));
+          mma<PREC>(acc[s], A, Bp);
+          continue;
+        }
         if constexpr (ORDER >= 5) {
           if (info & 0x40) A = form_rows<PREC, ORDER == 6 ? 3 : 2>(S + 32 * h, lv[2 * s], g);
           const Operand<PREC> Bop = form_rows<PREC, 3>(S + 32 * h, lv[2 * s + 1], g);

@@ -38,7 +38,10 @@ hipError_t launch_contract(int prec, int order, const CtrParams& p, int n_groups
 #define BY_PREC(O) do { if (prec == kFP32) BY_MB(kFP32, O); else if (prec == kBF16) BY_MB(kBF16, O); else BY_MB(kFP16, O); } while (0)
   if (order == 2) BY_PREC(2);
   else if (order == 3) BY_PREC(3);
-  else if (order == 4) BY_PREC(4);
+  else if (order == 4 && prec == kFP16 && p.n_pair_blocks > 0) {
+    if (p.n_pair_blocks > kMaxPairBlocksHost || p.n_blk > 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((contract_tiles<kFP16, 4, 4, true>), grid, dim3(kCtrThreads), 0, st, p);
+  } else if (order == 4) BY_PREC(4);
   else return hipErrorInvalidValue;
 #undef BY_PREC
 #undef BY_MB

@@ -41,6 +41,7 @@ struct CtrParams {
   const int* slot_uni;     // [n_groups][waves][kSlots / 4]: one byte per slot
   const int* slot_lane;    // [n_groups][waves][16 rows][kSlots]: pair shells per lane
   const int* slot_tile;
+  const int* slot_blk;     // [n_groups][waves][kSlotsMax]: A pair block | B pair block << 16
   const unsigned* absmax;
   float* partials;
   long long G;
@@ -50,7 +51,11 @@ struct CtrParams {
   int n_tiles;
   int ksteps;
   int n_chunks;
+  int n_pair_blocks;       // order 4, FP16: pair operands formed once per K-step in LDS (0: per slot)
 };
+// Order 4, split FP16: pair blocks that fit the workgroup's LDS as shared operands
+// beside the staged shell operands (28 blocks of 16 pairs: up to 29 shells).
+constexpr int kMaxPairBlocksHost = 28;
 constexpr int kCtrWavesHost = 16;
 constexpr int kSlotsHost = 14;
 constexpr int kSlots4Host = 10;

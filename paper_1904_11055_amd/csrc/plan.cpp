@@ -105,7 +105,8 @@ struct polyspec_plan_s {
   int n_tiles_j = 0, ksteps_j = 0, n_chunks_j = 0;
 
   // device tables
-  DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_lane_d, slot_tile_d, ent_d, bins_d, fnorm_d, lookup_d, wmask_d, flag_d;
+  DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_lane_d, slot_tile_d, slot_blk_d, ent_d, bins_d, fnorm_d, lookup_d,
+      wmask_d, flag_d;
   DevBuf jtile_d, jmask_d, ent_j_d;
   DevBuf closing_of_ent_d, closing_of_ent_j_d;   // streamed plans: tile entry -> closing tuple (or -1)
   // workspace carving
@@ -520,6 +521,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
   std::vector<int> uni((size_t)p->n_groups * ps::kCtrWavesHost * (S / 4), 0);
   std::vector<int> lanew((size_t)p->n_groups * ps::kCtrWavesHost * 16 * S, 0);
   std::vector<int> slot_tile((size_t)p->n_groups * ps::kCtrWavesHost * S, -1);
+  std::vector<int> slot_blk((size_t)p->n_groups * ps::kCtrWavesHost * S, 0);   // A | B << 16 pair blocks
   auto uv8 = [&](int pair) {
     const int w = p->pair_uv[pair];
     return (w & 0xff) | (((w >> 16) & 0xff) << 8);
@@ -542,6 +544,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
           prev_a = k.a;
           info = (n >= 4 ? 0 : (k.b & 7)) | (n == 2 ? (k.a & 7) << 3 : 0) | (form << 6);
           slot_tile[gw * S + s] = tl[s];
+          slot_blk[gw * S + s] = k.a | (k.b << 16);
           for (int r = 0; r < 16; ++r) {
             int* row_words = &lanew[(gw * 16 + r) * S];
             if (n == 3) row_words[s / 2] |= uv8(16 * k.a + r) << (16 * (s % 2));
@@ -558,6 +561,7 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
   PS_TRY(upload(p, &p->slots_d, uni));
   PS_TRY(upload(p, &p->slot_lane_d, lanew));
   PS_TRY(upload(p, &p->slot_tile_d, slot_tile));
+  PS_TRY(upload(p, &p->slot_blk_d, slot_blk));
   PS_TRY(upload(p, &p->pairs_d, p->pair_uv));
   return POLYSPEC_OK;
 }
@@ -905,7 +909,7 @@ void release(polyspec_plan_s* p) {
   p->ev_pending.clear();
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   p->ev_pool.clear();
-  DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_lane_d, &p->slot_tile_d, &p->ent_d,
+  DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_lane_d, &p->slot_tile_d, &p->slot_blk_d, &p->ent_d,
                     &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->jtile_d, &p->jmask_d,
                     &p->ent_j_d, &p->closing_of_ent_d, &p->closing_of_ent_j_d, &p->own_ws};
   for (DevBuf* b : bufs) dev_free(b);
@@ -1119,6 +1123,7 @@ static polyspec_status contract_launch(polyspec_plan_t p, bool accumulate, long 
     cp.slot_uni = (const int*)p->slots_d.p;
     cp.slot_lane = (const int*)p->slot_lane_d.p;
     cp.slot_tile = (const int*)p->slot_tile_d.p;
+    cp.slot_blk = (const int*)p->slot_blk_d.p;
     cp.absmax = p->absmax;
     cp.partials = p->partials;
     cp.G = launch_points(p);
@@ -1128,6 +1133,10 @@ static polyspec_status contract_launch(polyspec_plan_t p, bool accumulate, long 
     cp.n_tiles = p->n_tiles;
     cp.ksteps = p->ksteps;
     cp.n_chunks = p->n_chunks;
+    // order 4 in split FP16: every pair operand formed once per K-step, shared through LDS
+    const int npb = p->n_pairs_padded / 16;
+    cp.n_pair_blocks = (p->order == 4 && p->prec == POLYSPEC_SPLIT_FP16 && p->n_blk <= 4 && npb <= ps::kMaxPairBlocksHost)
+                           ? npb : 0;
     PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
     *n_ent = (long long)p->n_tiles * 256;
     n_chunks = p->n_chunks;
