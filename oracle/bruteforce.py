@@ -31,12 +31,13 @@ def shell_vectors(N: int, n_shells: int, width: float):
 
 
 def bruteforce_polyspectrum(delta: np.ndarray, order: int, n_shells: int, width: float,
-                            tuples) -> tuple[np.ndarray, np.ndarray]:
+                            tuples, last_weight=None) -> tuple[np.ndarray, np.ndarray]:
     """(count, sum of prod delta_hat) for each tuple, by explicit enumeration.
 
     delta_hat is the unnormalised forward DFT of the real field; the returned sums
     are complex (their imaginary parts vanish up to rounding because the set of
-    closed tuples is symmetric under q -> -q).
+    closed tuples is symmetric under q -> -q).  last_weight(q) (an array of wave
+    vectors -> weights) multiplies each product by a weight of the last vector.
     """
     delta = np.asarray(delta, dtype=np.float64)
     N = delta.shape[0]
@@ -70,6 +71,8 @@ def bruteforce_polyspectrum(delta: np.ndarray, order: int, n_shells: int, width:
             ok = shell_of_squared_norm((q_last ** 2).sum(-1), n_shells, width) == last
             va = value(a) if order > 2 else np.ones(1)
             prod = w * va[:, None] * value(b)[None, :] * value(q_last)
+            if last_weight is not None:
+                prod = prod * last_weight(q_last)
             cnt += int(ok.sum())
             acc += prod[ok].sum()
         counts[n] = cnt

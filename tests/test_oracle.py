@@ -433,3 +433,54 @@ def test_gradient_on_a_shell_subset_matches_full():
     with pytest.raises(ValueError):
         O.gradient_spectrum(N, order, nb, 1.0, r["tuples"], r["counts"], r["fields"][np.array(sub) - 1],
                             np.ones(len(r["tuples"])), shells=sub)
+
+
+# ---------------------------------------------------------------------------------------
+# Redshift-space multipoles (Sec. 5: the estimator on multipole-weighted fields)
+# ---------------------------------------------------------------------------------------
+def test_multipole_zero_is_the_monopole_of_every_leg():
+    """ell = 0 weights nothing: B_0(u, v; w) is the monopole of the sorted triangle."""
+    delta = fieldgen.gaussian_field(32, 61)
+    mono = O.polyspectrum(delta, 3, 6, 1.0)
+    m0 = O.bispectrum_multipoles(delta, 6, 1.0, 0)
+    lut = {tuple(t): b for t, b in zip(mono["tuples"].tolist(), mono["B"])}
+    ref = np.array([lut[tuple(sorted(t))] for t in m0["tuples"].tolist()])
+    np.testing.assert_allclose(m0["B"], ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    # every closing triangle appears once per distinct weighted side
+    n_sides = sum(len(set(t)) for t in mono["tuples"].tolist())
+    assert len(m0["tuples"]) == n_sides
+
+
+def test_multipole_equals_direct_enumeration_with_the_legendre_weight():
+    """B_2 against explicit enumeration of the closed triangles, each weighted by
+    L_2(mu) of its last vector, mu the cosine to the third grid axis."""
+    N, nb, width, ell = 16, 3, 1.0, 2
+    delta = fieldgen.gaussian_field(N, 62)
+    r = O.bispectrum_multipoles(delta, nb, width, ell)
+
+    def weight(q):
+        norm = np.sqrt((q.astype(np.float64) ** 2).sum(-1))
+        mu = np.where(norm > 0, q[..., 2] / np.where(norm > 0, norm, 1.0), 0.0)
+        return (3.0 * mu ** 2 - 1.0) / 2.0      # L_2, written out
+
+    cnt, sums = O.bruteforce_polyspectrum(delta, 3, nb, width, r["tuples"], last_weight=weight)
+    assert np.array_equal(cnt, r["counts"])
+    scale = np.abs(sums).max()
+    assert np.abs(sums.imag).max() <= 1e-12 * scale
+    np.testing.assert_allclose(sums.real * N ** 3, r["sums"], rtol=0, atol=1e-12 * scale * N ** 3)
+    np.testing.assert_allclose(5.0 * sums.real / cnt, r["B"], rtol=1e-10, atol=1e-12 * np.abs(r["B"]).max())
+
+
+def test_quadrupoles_about_the_three_axes_sum_to_zero():
+    """sum over the three axes of L_2(mu_axis) = (3 |q|^2 / |q|^2 - 3) / 2 = 0 for every
+    mode, so the three quadrupoles of any field cancel exactly."""
+    delta = fieldgen.lognormal_field(24, 63)
+    parts = [O.bispectrum_multipoles(delta, 5, 1.0, 2, axis=a)["B"] for a in range(3)]
+    total = parts[0] + parts[1] + parts[2]
+    assert np.abs(total).max() <= 1e-11 * max(np.abs(p).max() for p in parts)
+    assert np.abs(parts[2]).max() > 1e-3 * np.abs(O.polyspectrum(delta, 3, 5, 1.0)["B"]).max()
+
+
+def test_odd_multipoles_are_refused():
+    with pytest.raises(ValueError):
+        O.bispectrum_multipoles(fieldgen.gaussian_field(16, 64), 3, 1.0, 1)
