@@ -67,7 +67,8 @@ enum {
   POLYSPEC_INPUT_HALF_SPECTRUM = 1u, /* polyspec_shells input is delta_hat, complex64 [batch][N][N][N/2+1] */
   POLYSPEC_ALLOW_ALIASING = 2u,      /* accept order*(n_shells+1/2)*width > N: exact mod-N estimator */
   POLYSPEC_NAN_GUARD = 8u,           /* contract reports POLYSPEC_ERR_DEVICE on a non-finite output */
-  POLYSPEC_STREAM_SLABS = 16u        /* shell fields are never stored whole: see polyspec_set_slab_planes */
+  POLYSPEC_STREAM_SLABS = 16u,       /* shell fields are never stored whole: see polyspec_set_slab_planes */
+  POLYSPEC_MULTIPOLE = 32u           /* order 3: bispectrum multipoles about the third axis, see polyspec_set_multipole */
 };
 
 typedef struct {
@@ -143,6 +144,20 @@ polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out
 #define POLYSPEC_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 polyspec_status polyspec_forward_static(polyspec_plan_t plan, const void* d_delta, double* d_out,
                                         double* d_raw_sums);
+
+/* Redshift-space bispectrum multipoles (Sec. 5: the estimator on multipole-weighted
+ * fields).  A plan made with POLYSPEC_MULTIPOLE (order 3, at most 64 shells, not
+ * streamed) has one output tuple (u, v, w), u <= v, for each closing triangle and each
+ * distinct choice of its weighted side w; polyspec_tuples lists them (w last) in
+ * lexicographic order with the triangle's count.  With the line of sight along the
+ * third grid axis and mu = q2 / |q|, the output is
+ *   B_ell(u, v; w) = (2 ell + 1) f sum_x d_u d_v d^ell_w / (N^3 n_t),
+ * d^ell_w the shell field of delta_hat L_ell(mu).  The plan keeps 2 N_b fields (the
+ * shells, then their weighted copies; polyspec_fields returns both).  ell: even, 0 to
+ * 16 (odd ell would make the weighted fields imaginary); 0 until set.  Setting it
+ * invalidates the fields: call polyspec_shells again.  POLYSPEC_ERR_STATE for a plan
+ * without the flag; polyspec_backward is not available for these plans. */
+polyspec_status polyspec_set_multipole(polyspec_plan_t plan, int32_t ell);
 
 /* Bytes of device workspace the plan needs for shells, contract and backward. */
 polyspec_status polyspec_workspace_size(polyspec_plan_t plan, size_t* bytes);

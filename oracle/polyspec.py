@@ -626,9 +626,8 @@ def bispectrum_multipoles(delta: np.ndarray, n_shells: int, width: float, ell: i
     mono = polyspectrum(delta, 3, n_shells, width, counts=counts, return_fields=True)
     tup, n = multipole_tuples(mono["tuples"], mono["counts"])
     dl = multipole_fields_from_hat(rfftn(delta), N, n_shells, width, ell, axis)
-    d = mono["fields"]
-    S = np.empty(len(tup))
-    for k, (u, v, w) in enumerate(tup):
-        S[k] = float(np.sum(d[u - 1] * d[v - 1] * dl[w - 1]))
+    # the weighted fields follow the shells: (u, v, w) is the plain triple (u, v, n_shells + w)
+    stacked = np.concatenate([mono["fields"], dl])
+    S = product_sums(stacked, tup + np.array([0, 0, n_shells]))
     B = (2 * ell + 1) * physical_factor(3, N, box_length) * S / (float(N) ** 3 * n)
     return dict(tuples=tup, counts=n, sums=S, B=B)

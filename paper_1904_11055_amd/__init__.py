@@ -20,9 +20,9 @@ import numpy as np
 
 __all__ = [
     "PolyspecError", "Plan", "polyspectrum", "load_library",
-    "FP32", "SPLIT_BF16", "SPLIT_FP16", "INPUT_HALF_SPECTRUM", "ALLOW_ALIASING", "NAN_GUARD", "STREAM_SLABS",
+    "FP32", "SPLIT_BF16", "SPLIT_FP16", "INPUT_HALF_SPECTRUM", "ALLOW_ALIASING", "NAN_GUARD", "STREAM_SLABS", "MULTIPOLE",
     "polyspec_plan", "polyspec_shells", "polyspec_contract", "polyspec_backward", "polyspec_forward_static",
-    "polyspec_workspace_size", "polyspec_set_workspace", "polyspec_set_precision",
+    "polyspec_workspace_size", "polyspec_set_workspace", "polyspec_set_precision", "polyspec_set_multipole",
     "polyspec_set_slab_planes", "polyspec_slab_planes",
     "polyspec_tuples", "polyspec_candidates", "polyspec_fields", "polyspec_destroy",
     "polyspec_profile", "polyspec_profile_read", "PHASES",
@@ -31,7 +31,7 @@ __all__ = [
 
 FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2
 STATIC_SCRATCH_BYTES = 128 << 20   # POLYSPEC_STATIC_SCRATCH_BYTES
-INPUT_HALF_SPECTRUM, ALLOW_ALIASING, NAN_GUARD, STREAM_SLABS = 1, 2, 8, 16
+INPUT_HALF_SPECTRUM, ALLOW_ALIASING, NAN_GUARD, STREAM_SLABS, MULTIPOLE = 1, 2, 8, 16, 32
 
 STATUS = {0: "POLYSPEC_OK", 1: "POLYSPEC_ERR_INVALID_ARG", 2: "POLYSPEC_ERR_ALIASING",
           3: "POLYSPEC_ERR_OUT_OF_MEMORY", 4: "POLYSPEC_ERR_DEVICE",
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "polyspec_workspace_size": (ctypes.c_int, [P, D(ctypes.c_size_t)]),
         "polyspec_set_workspace": (ctypes.c_int, [P, V, ctypes.c_size_t]),
         "polyspec_set_precision": (ctypes.c_int, [P, ctypes.c_int32]),
+        "polyspec_set_multipole": (ctypes.c_int, [P, ctypes.c_int32]),
         "polyspec_set_slab_planes": (ctypes.c_int, [P, ctypes.c_int32]),
         "polyspec_slab_planes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
         "polyspec_tuples": (ctypes.c_int, [P, D(ctypes.c_int64), V, V]),
@@ -159,6 +160,10 @@ def polyspec_set_precision(plan, precision: int):
     _check(load_library().polyspec_set_precision(plan, precision), "polyspec_set_precision", plan)
 
 
+def polyspec_set_multipole(plan, ell: int):
+    _check(load_library().polyspec_set_multipole(plan, ell), "polyspec_set_multipole", plan)
+
+
 def polyspec_set_slab_planes(plan, planes: int):
     _check(load_library().polyspec_set_slab_planes(plan, planes), "polyspec_set_slab_planes", plan)
 
@@ -233,8 +238,12 @@ class Plan:
     """One geometry (grid, order, shells) and batch, bound to torch's current stream."""
 
     def __init__(self, N, order, n_shells, shell_width, batch=1, precision=FP32, box_length=0.0,
-                 flags=0, device=None, slab_planes=None):
+                 flags=0, device=None, slab_planes=None, multipole=None):
+        """multipole=ell (even, 0..16) selects the bispectrum multipole B_ell about the third grid
+        axis: the plan's tuples are then (u, v, w) with the Legendre weight on shell w."""
         import torch
+        if multipole is not None:
+            flags |= MULTIPOLE
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.N, self.order, self.n_shells, self.width = N, order, n_shells, float(shell_width)
         self.batch, self.flags = batch, flags
@@ -243,6 +252,9 @@ class Plan:
             self.stream = torch.cuda.current_stream(self.device)
             self.handle = polyspec_plan(N, order, n_shells, shell_width, batch, precision, box_length,
                                         flags, ctypes.c_void_p(self.stream.cuda_stream))
+        self._multipole = None
+        if multipole is not None:
+            self.multipole = multipole
         if slab_planes is not None:
             polyspec_set_slab_planes(self.handle, slab_planes)
         self.slab_planes = polyspec_slab_planes(self.handle)
@@ -271,6 +283,16 @@ class Plan:
     def precision(self, value):
         polyspec_set_precision(self.handle, value)
         self._precision = value
+
+    @property
+    def multipole(self):
+        return self._multipole
+
+    @multipole.setter
+    def multipole(self, ell):
+        """Switches a MULTIPOLE plan to another even ell; the next shells() recomputes the fields."""
+        polyspec_set_multipole(self.handle, ell)
+        self._multipole = ell
 
     def candidates(self):
         return polyspec_candidates(self.handle, self.order)
@@ -314,10 +336,12 @@ class Plan:
         return g
 
     def fields(self):
-        """A copy of the kept float32 shell fields [batch, n_shells, N, N, N]."""
+        """A copy of the kept float32 shell fields [batch, n_fields, N, N, N] (n_fields is
+        n_shells, or 2 n_shells for a multipole plan: the shells, then their weighted copies)."""
         import torch
         ptr = polyspec_fields(self.handle)
-        shape = (self.batch, self.n_shells, self.N, self.N, self.N)
+        n_fields = self.n_shells * (2 if self.flags & MULTIPOLE else 1)
+        shape = (self.batch, n_fields, self.N, self.N, self.N)
         view = torch.as_tensor(_DeviceArray(ptr, shape, "<f4"), device=self.device)
         return view.clone()
 

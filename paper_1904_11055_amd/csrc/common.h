@@ -49,10 +49,28 @@ struct Geom {
   int n_shells;
   int S1;     // x1 planes of the slab (N for the whole grid)
   int x1_0;   // first x1 plane of the slab
+  int fold;   // fields per shell set: field f of a batch is shell shell_base + f % fold
+  int ell;    // multipole plans: fields f >= fold carry the weight L_ell(mu); -1 otherwise
 };
 
 __device__ __forceinline__ int geom_shell(const Geom& g, int z) {
-  return g.spb > 0 ? g.shell_base + z % g.spb : 0;
+  return g.spb > 0 ? g.shell_base + (z % g.spb) % g.fold : 0;
+}
+// Multipole plans: whether field z is the Legendre-weighted copy of its shell.
+__device__ __forceinline__ bool geom_weighted(const Geom& g, int z) {
+  return g.ell >= 0 && g.spb > 0 && (z % g.spb) >= g.fold;
+}
+// Legendre polynomial L_ell(mu) by the three-term recurrence.
+template <typename T>
+__device__ __forceinline__ T legendre(int ell, T mu) {
+  T p0 = (T)1, p1 = mu;
+  if (ell == 0) return p0;
+  for (int n = 1; n < ell; ++n) {
+    const T p2 = ((T)(2 * n + 1) * mu * p1 - (T)n * p0) / (T)(n + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
 }
 __device__ __forceinline__ int geom_batch(const Geom& g, int z) {
   return g.spb > 0 ? z / g.spb : z;

@@ -48,6 +48,8 @@ __device__ __forceinline__ int freq_of(int n, int N) { return n < N / 2 ? n : n 
 
 // P1: columns (a, c) of the box, transform q1 -> x1, masked by shell s(z).
 // UNIT: the input is the unit shell (1 inside, 0 outside) instead of the box.
+// Multipole plans: the weighted fields also take L_ell(mu), mu = q2 / |q| (the line of
+// sight along the third axis; q2 is the column index c).
 // grid (ceil(B0/P), B2, nz)
 template <typename T, int N, bool UNIT>
 __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restrict__ box,
@@ -63,6 +65,7 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restr
   const int z = blockIdx.z;
   const int s = geom_shell(g, z);
   const int b = geom_batch(g, z);
+  const bool weighted = !UNIT && geom_weighted(g, z);
   const int a0 = blockIdx.x * P;
   const int c = blockIdx.y;
   const int Kc = g.Kc;
@@ -96,6 +99,11 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p1(const cplx<float>* __restr
             cplx<float> v = bx[((size_t)a * g.B2 + c) * g.B0 + (q1 + Kc)];
             val.re = (T)v.re;
             val.im = (T)v.im;
+            if (weighted) {
+              const T lw = legendre<T>(g.ell, (T)c / sqrt((T)Q));
+              val.re *= lw;
+              val.im *= lw;
+            }
           }
         }
       }

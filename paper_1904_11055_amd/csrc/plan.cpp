@@ -93,6 +93,13 @@ struct polyspec_plan_s {
   std::vector<int> closing;        // candidate index of each closing tuple
   std::vector<int> cl_bins;        // [n_closing][order]
   std::vector<int64_t> cl_counts;
+  std::vector<double> fnorm_base;  // f / (N^3 n_t) of each closing tuple
+
+  // multipole plans (POLYSPEC_MULTIPOLE): nb counts fields, ns shells; fields 0..ns-1 are
+  // the shells, ns..2ns-1 their L_ell-weighted copies, and tuples are (u, v, ns + w)
+  bool mp = false;
+  int ns = 0;
+  int ell = 0;
 
   // contraction tiling
   int n_pairs = 0, n_pairs_padded = 0, n_tiles = 0, n_groups = 0, ksteps = 0, n_chunks = 0;
@@ -224,6 +231,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // The adjoint product exists for order 3 up to 64 shells and order 4 up to 32.
 bool has_adjoint(const polyspec_plan_s* p) {
+  if (p->mp) return false;
   return (p->order == 3 && p->nb <= ps::kAdj3MaxShells) || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
 }
 
@@ -238,6 +246,8 @@ Geom make_geom(const polyspec_plan_s* p, int spb, int shell_base) {
   g.n_shells = p->nb;
   g.S1 = p->N;
   g.x1_0 = 0;
+  g.fold = p->mp ? p->ns : std::max(spb, 1);
+  g.ell = p->mp ? p->ell : -1;
   return g;
 }
 
@@ -732,6 +742,35 @@ polyspec_status compute_counts(polyspec_plan_s* p) {
   return st;
 }
 
+// Multipole plans: every closing-candidate triangle (a <= b <= c) of the shells gives a
+// tuple for each distinct choice of its weighted side w, (u, v, ns + w) with (u, v) the
+// other two sides in order, over the 2 ns fields; lexicographic order, the triangle's
+// count and quotient.
+void expand_multipoles(polyspec_plan_s* p) {
+  const int ns = p->ns;
+  std::map<std::array<int, 3>, std::pair<int64_t, double>> rows;
+  const size_t nc = p->cand.size() / 3;
+  for (size_t c = 0; c < nc; ++c) {
+    const int a = p->cand[3 * c], b = p->cand[3 * c + 1], e = p->cand[3 * c + 2];
+    const std::pair<int64_t, double> v{p->cand_count[c], p->cand_quot[c]};
+    rows[{b, e, a}] = v;
+    rows[{a, e, b}] = v;
+    rows[{a, b, e}] = v;
+  }
+  p->cand.clear();
+  p->cand_count.clear();
+  p->cand_quot.clear();
+  for (const auto& kv : rows) {
+    p->cand.push_back(kv.first[0]);
+    p->cand.push_back(kv.first[1]);
+    p->cand.push_back(ns + kv.first[2]);
+    p->cand_count.push_back(kv.second.first);
+    p->cand_quot.push_back(kv.second.second);
+  }
+  p->nb = 2 * ns;
+  p->n_blk = (p->nb + 15) / 16;
+}
+
 polyspec_status build_plan(polyspec_plan_s* p) {
   const polyspec_desc& d = p->desc;
   if (d.N < 32 || d.N > 1024 || (d.N & (d.N - 1)) != 0)
@@ -742,8 +781,8 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   if (d.precision < 0 || d.precision > 2) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown precision");
   if (!(d.box_length >= 0.0) || !std::isfinite(d.box_length))
     return p->fail(POLYSPEC_ERR_INVALID_ARG, "box_length must be finite and >= 0");
-  const uint32_t known =
-      POLYSPEC_INPUT_HALF_SPECTRUM | POLYSPEC_ALLOW_ALIASING | POLYSPEC_NAN_GUARD | POLYSPEC_STREAM_SLABS;
+  const uint32_t known = POLYSPEC_INPUT_HALF_SPECTRUM | POLYSPEC_ALLOW_ALIASING | POLYSPEC_NAN_GUARD |
+                         POLYSPEC_STREAM_SLABS | POLYSPEC_MULTIPOLE;
   if (d.flags & ~known) return p->fail(POLYSPEC_ERR_INVALID_ARG, "unknown flag bits");
   Dyadic w;
   if (!to_dyadic(d.shell_width, &w)) return p->fail(POLYSPEC_ERR_INVALID_ARG, "shell_width must be finite and > 0");
@@ -751,7 +790,15 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     return p->fail(POLYSPEC_ERR_INVALID_ARG, "shell_width must be a binary fraction with at most 24 significant bits");
   p->N = d.N;
   p->order = d.order;
-  p->nb = d.n_shells;
+  p->nb = d.n_shells;   // shells; a multipole plan doubles it into fields once its counts are known
+  p->ns = d.n_shells;
+  p->mp = (d.flags & POLYSPEC_MULTIPOLE) != 0;
+  if (p->mp) {
+    if (d.order != 3) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "multipoles are implemented for order 3");
+    if (d.flags & POLYSPEC_STREAM_SLABS) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "multipole plans are not streamed");
+    if (2 * d.n_shells > 16 * ps::kMaxTileBlkHost)
+      return p->fail(POLYSPEC_ERR_UNSUPPORTED, "a multipole plan handles at most 64 shells");
+  }
   p->batch = d.batch;
   p->prec = d.precision;
   p->G = (long long)d.N * d.N * d.N;
@@ -795,6 +842,13 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   for (int s = 1; s <= p->nb; ++s) p->qmax[s] = (int)(p->thr[s] - 1);
 
   build_tuples(p);
+  if (p->mp) {
+    // the triangles' counts over the shells first, then the weighted-leg tuples
+    PS_TRY(upload(p, &p->shell_q, p->shell_of_q));
+    PS_TRY(upload(p, &p->qmax_d, p->qmax));
+    PS_TRY(compute_counts(p));
+    expand_multipoles(p);
+  }
   std::vector<int> ent_of_cand;
   PS_TRY(build_tiles(p, &ent_of_cand));
   std::vector<int> ent_j_of_cand;
@@ -813,9 +867,11 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   set_chunking(p);
 
   PS_TRY(upload(p, &p->tw32, twiddles<float>(p->N)));
-  PS_TRY(upload(p, &p->shell_q, p->shell_of_q));
-  PS_TRY(upload(p, &p->qmax_d, p->qmax));
-  PS_TRY(compute_counts(p));
+  if (!p->mp) {
+    PS_TRY(upload(p, &p->shell_q, p->shell_of_q));
+    PS_TRY(upload(p, &p->qmax_d, p->qmax));
+    PS_TRY(compute_counts(p));
+  }
 
   const size_t nc = p->cand.size() / p->order;
   std::vector<int> ent, ent_j;
@@ -827,7 +883,7 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     phys = std::pow(V, p->order - 1) / std::pow((double)p->N, 3 * p->order);
   }
   std::vector<int> lookup;
-  const bool adj3 = p->order == 3 && p->nb <= ps::kAdj3MaxShells, adj4 = p->order == 4 && p->nb <= ps::kAdj4MaxShells;
+  const bool adj3 = has_adjoint(p) && p->order == 3, adj4 = has_adjoint(p) && p->order == 4;
   if (adj3) lookup.assign((size_t)p->nb * p->nb * p->nb, -1);
   if (adj4) lookup.assign((size_t)p->nb * p->nb * p->nb * p->nb, -1);
   for (size_t c = 0; c < nc; ++c) {
@@ -838,7 +894,8 @@ polyspec_status build_plan(polyspec_plan_s* p) {
     p->cl_counts.push_back(p->cand_count[c]);
     ent.push_back(ent_of_cand[c]);
     if (p->jsched) ent_j.push_back(ent_j_of_cand[c]);
-    fnorm.push_back(phys / (N3 * (double)p->cand_count[c]));
+    fnorm.push_back(phys / (N3 * (double)p->cand_count[c]) * (p->mp ? 2.0 * p->ell + 1.0 : 1.0));
+    p->fnorm_base.push_back(phys / (N3 * (double)p->cand_count[c]));
     if (adj3) {
       const int* t = &p->cand[c * 3];
       lookup[((size_t)t[0] * p->nb + t[1]) * p->nb + t[2]] = k;
@@ -1254,7 +1311,8 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, v
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
   if (!has_adjoint(p))
     return p->fail(POLYSPEC_ERR_UNSUPPORTED,
-                   "backward is implemented for order 3 with at most 64 shells and order 4 with at most 32");
+                   "backward is implemented for order 3 with at most 64 shells and order 4 with at most 32 "
+                   "(not for multipole plans)");
   if (!d_grad_out || !d_grad_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null pointer");
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_backward before polyspec_shells");
   hipStream_t st = p->stream;
@@ -1332,8 +1390,8 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, v
 polyspec_status polyspec_tuples(polyspec_plan_t p, int64_t* n_closing, int32_t* h_bins, int64_t* h_counts) {
   if (!p || !n_closing) return POLYSPEC_ERR_INVALID_ARG;
   *n_closing = (int64_t)p->closing.size();
-  if (h_bins)
-    for (size_t i = 0; i < p->cl_bins.size(); ++i) h_bins[i] = p->cl_bins[i] + 1;
+  if (h_bins)   // 1-based shells (a multipole plan's last, weighted field reported as its shell)
+    for (size_t i = 0; i < p->cl_bins.size(); ++i) h_bins[i] = p->cl_bins[i] % (p->mp ? p->ns : 1 << 30) + 1;
   if (h_counts) std::memcpy(h_counts, p->cl_counts.data(), p->cl_counts.size() * sizeof(int64_t));
   return POLYSPEC_OK;
 }
@@ -1342,8 +1400,24 @@ polyspec_status polyspec_candidates(polyspec_plan_t p, int64_t* n_candidates, in
   if (!p || !n_candidates) return POLYSPEC_ERR_INVALID_ARG;
   *n_candidates = (int64_t)(p->cand.size() / p->order);
   if (h_bins)
-    for (size_t i = 0; i < p->cand.size(); ++i) h_bins[i] = p->cand[i] + 1;
+    for (size_t i = 0; i < p->cand.size(); ++i) h_bins[i] = p->cand[i] % (p->mp ? p->ns : 1 << 30) + 1;
   if (h_quotients) std::memcpy(h_quotients, p->cand_quot.data(), p->cand_quot.size() * sizeof(double));
+  return POLYSPEC_OK;
+}
+
+polyspec_status polyspec_set_multipole(polyspec_plan_t p, int32_t ell) {
+  if (!p) return POLYSPEC_ERR_INVALID_ARG;
+  if (!p->mp) return p->fail(POLYSPEC_ERR_STATE, "the plan was not made with POLYSPEC_MULTIPOLE");
+  if (ell < 0 || ell > 16 || (ell & 1)) return p->fail(POLYSPEC_ERR_INVALID_ARG, "ell must be even, 0 to 16");
+  std::vector<double> fnorm(p->fnorm_base.size());
+  for (size_t k = 0; k < fnorm.size(); ++k) fnorm[k] = p->fnorm_base[k] * (2.0 * ell + 1.0);
+  // on the plan's stream, after any gather still reading the factors
+  PS_HIP(p, hipMemcpyAsync(p->fnorm_d.p, fnorm.data(), fnorm.size() * sizeof(double), hipMemcpyHostToDevice,
+                           p->stream));
+  PS_HIP(p, hipStreamSynchronize(p->stream));
+  p->ell = ell;
+  p->have_fields = false;   // the weighted fields of the previous ell are stale
+  p->absmax_valid = false;
   return POLYSPEC_OK;
 }
 
