@@ -386,12 +386,20 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
           f32x16 Y[kAdjPB];
           static_for<vc + 1>([&](auto ucc) {
             constexpr int uc = decltype(ucc)::value;
-            const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
-            const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
+            const bool on = (mask >> (2 * uc + mb)) & 1;   // a weight in block (uc, mb)
+            if (on) {
+              const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
+              const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
 #pragma unroll
-            for (int pb = 0; pb < kAdjPB; ++pb) {
-              if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
-              else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+              for (int pb = 0; pb < kAdjPB; ++pb) {
+                if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
+                else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+              }
+            } else if constexpr (uc == 0) {
+#pragma unroll
+              for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) Y[pb][i] = 0.f;
             }
           });
 #pragma unroll
