@@ -147,3 +147,23 @@ def test_multipole_switch_and_refusals(gpu):
         with pytest.raises(ps.PolyspecError) as e:
             ps.Plan(256 if nb == 65 else 32, order, nb, 1.0, flags=flags, multipole=0, device="cuda:0")
         assert e.value.status == 7, (order, flags, nb)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (2, 1e-4)])
+def test_multipole_batch_half_spectrum_and_box_length(gpu, precision, tol):
+    """A batch of two fields given as half spectra, with physical units: each member
+    against the oracle's quadrupole of its own field."""
+    import torch
+    ps = _ps()
+    N, nb, L = 32, 7, 500.0
+    fields = [fieldgen.lognormal_field(N, 75 + i).astype(np.float32) for i in range(2)]
+    hs = np.stack([np.fft.rfftn(f.astype(np.float64)).astype(np.complex64) for f in fields])
+    plan = ps.Plan(N, 3, nb, 1.0, batch=2, precision=precision, flags=ps.INPUT_HALF_SPECTRUM, box_length=L,
+                   multipole=2, device="cuda:0")
+    plan.shells(torch.from_numpy(hs).to("cuda:0"))
+    B = plan.contract().cpu().numpy()
+    for i, f in enumerate(fields):
+        ref = O.bispectrum_multipoles(f.astype(np.float64), nb, 1.0, 2, box_length=L)
+        assert np.array_equal(plan.tuples, ref["tuples"])
+        assert _rel(B[i], ref["B"]) < tol, i
+    plan.close()
