@@ -275,6 +275,35 @@ __device__ __forceinline__ void adj_unscale(f32x16 (&acc)[kAdjPB][kAdjMaxMb], co
   }
 }
 
+// One partner v of the order-3 adjoint: Y[mb] = sum over the chunks uc <= VC of the
+// weight block (uc, mb) times the field operands, for the first NM m-blocks, then
+// a_m += d_v Y[mb].  Straight-line code, so that the multiply-adds of one m-block are
+// scheduled under the products of the next.
+template <int PREC, int NM, int VC>
+__device__ __forceinline__ void adj_partner(f32x16 (&acc)[kAdjPB][kAdjMaxMb], const float (&dv)[kAdjPB],
+                                            const uint4* wv, const Operand<PREC> (&fop)[kAdjPB][4], int lane) {
+  f32x16 Y[NM][kAdjPB];
+  static_for<NM>([&](auto mbc) {
+    constexpr int mb = decltype(mbc)::value;
+    static_for<VC + 1>([&](auto ucc) {
+      constexpr int uc = decltype(ucc)::value;
+      const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
+      const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
+#pragma unroll
+      for (int pb = 0; pb < kAdjPB; ++pb) {
+        if constexpr (uc == 0) adj_mma_first<PREC>(Y[mb][pb], Wop, fop[pb][uc]);
+        else adj_mma<PREC>(Y[mb][pb], Wop, fop[pb][uc]);
+      }
+    });
+  });
+#pragma unroll
+  for (int mb = 0; mb < NM; ++mb)
+#pragma unroll
+    for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[pb][mb][i] = fmaf(dv[pb], Y[mb][pb][i], acc[pb][mb][i]);
+}
+
 // Order 3.  A workgroup of 8 waves owns 512 grid points (each wave two 32-point
 // column blocks) and every m.  For each partner v and 32-row block mb of m,
 // Y = sum over the chunks uc <= v / 16 of W_v[uc, mb] d_u runs on the matrix cores with
@@ -380,32 +409,38 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
           else
             dv[pb] = __uint_as_float(w);
         }
+        if constexpr (PREC != kFP16 && vc > 0) {
+          adj_partner<PREC, MBN, vc>(acc, dv, wv, fop, lane);   // every block, straight-line
+        } else {
+          // blocks (uc, mb) without a weight skipped (v < 16: one chunk, and m-block 1
+          // rarely holds a weight; FP16: the straight-line form spills registers)
 #pragma unroll
-        for (int mb = 0; mb < MBN; ++mb) {
-          if (!(mask & (0x55 << mb))) continue;   // no weight in this block of m
-          f32x16 Y[kAdjPB];
-          static_for<vc + 1>([&](auto ucc) {
-            constexpr int uc = decltype(ucc)::value;
-            const bool on = (mask >> (2 * uc + mb)) & 1;   // a weight in block (uc, mb)
-            if (on) {
-              const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
-              const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
+          for (int mb = 0; mb < MBN; ++mb) {
+            if (!(mask & (0x55 << mb))) continue;   // no weight in this block of m
+            f32x16 Y[kAdjPB];
+            static_for<vc + 1>([&](auto ucc) {
+              constexpr int uc = decltype(ucc)::value;
+              const bool on = (mask >> (2 * uc + mb)) & 1;   // a weight in block (uc, mb)
+              if (on) {
+                const uint4* blk = wv + (uc * kAdjMaxMb + mb) * 2 * 64;
+                const Operand<PREC> Wop = op_from_words<PREC>(blk[lane], blk[64 + lane]);
 #pragma unroll
-              for (int pb = 0; pb < kAdjPB; ++pb) {
-                if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
-                else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+                for (int pb = 0; pb < kAdjPB; ++pb) {
+                  if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
+                  else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+                }
+              } else if constexpr (uc == 0) {
+#pragma unroll
+                for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+                  for (int i = 0; i < 16; ++i) Y[pb][i] = 0.f;
               }
-            } else if constexpr (uc == 0) {
+            });
 #pragma unroll
-              for (int pb = 0; pb < kAdjPB; ++pb)
+            for (int pb = 0; pb < kAdjPB; ++pb)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) Y[pb][i] = 0.f;
-            }
-          });
-#pragma unroll
-          for (int pb = 0; pb < kAdjPB; ++pb)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[pb][mb][i] = fmaf(dv[pb], Y[pb][i], acc[pb][mb][i]);
+              for (int i = 0; i < 16; ++i) acc[pb][mb][i] = fmaf(dv[pb], Y[pb][i], acc[pb][mb][i]);
+          }
         }
       }
       if (more && (vi == kAdjVG - 1)) {
