@@ -128,7 +128,7 @@ __device__ __forceinline__ void adjoint_epilogue(const f32x16 (&acc)[kAdjPB][kAd
       cplx<float> v;
       if ((r & 1) == 0) v = cplx<float>{0.5f * (Zp.re + Zm.re), 0.5f * (Zp.im - Zm.im)};
       else v = cplx<float>{0.5f * (Zp.im + Zm.im), 0.5f * (Zm.re - Zp.re)};
-      H2[((size_t)(b * n_shells + m) * (G / NF) + row0 + rho) * g.B2 + c] = v;   // G / NF rows per field
+      H2[((size_t)(b * n_shells + m) * (G / NF) + row0 + rho) * g.H2s + c] = v;   // G / NF rows per field
     }
   }
 }

@@ -32,7 +32,9 @@ __device__ __forceinline__ cplx<T> cmul_i(cplx<T> a, int s) {
 // [a = q0 + Kc][c = q2][e = q1 + Kc] (half space q2 >= 0), Kc the largest integer
 // component below K_e.  Intermediates between 1-D passes:
 //   H1[z][x1][c][a]   (after the q1 -> x1 transform),  N * B2 * B0 values
-//   H2[z][x0][x1][c]  (after the q0 -> x0 transform),  N * N * B2 values
+//   H2[z][x0][x1][c]  (after the q0 -> x0 transform),  N * N * H2s values: rows of B2
+//                     entries at a stride H2s of B2 rounded up to 16, so that the runs of
+//                     16 consecutive c written by the q0 -> x0 pass are whole 128-byte lines
 // A slab restricts the last two transforms to the planes x1_0 <= x1 < x1_0 + S1 (the
 // whole grid is the slab x1_0 = 0, S1 = N): H2 and the real output then hold S1
 // planes, [z][x0][x1 - x1_0][c] and [z][x0][x1 - x1_0][x2].
@@ -44,6 +46,7 @@ struct Geom {
   int Kc;
   int B0;   // 2Kc+1 (also the q1 extent of the box)
   int B2;   // Kc+1
+  int H2s;  // row stride of H2: B2 rounded up to a multiple of 16
   int spb;
   int shell_base;
   int n_shells;

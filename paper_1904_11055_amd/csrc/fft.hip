@@ -159,13 +159,13 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p2(const cplx<T>* __restrict_
   }
   __syncthreads();
   fft_block<T, N, P, NS, +1>(buf, stw);
-  cplx<T>* out = H2 + (size_t)z * N * g.S1 * g.B2;
+  cplx<T>* out = H2 + (size_t)z * N * g.S1 * g.H2s;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x0 = u / P;
     const int c = c0 + pp;
-    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * g.S1 + xs) * g.B2 + c] = buf[pp * NS + pad8(x0)];
+    if (c < g.B2 && c * c <= qm) out[((size_t)x0 * g.S1 + xs) * g.H2s + c] = buf[pp * NS + pad8(x0)];
   }
 }
 
@@ -224,10 +224,10 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3(const cplx<float>* __restr
   for (int it = 0; it < REPS; ++it) {
   if (it > 0) __syncthreads();          // the previous group's output has left the LDS
   const int row0 = (blockIdx.x * REPS + it) * 2 * P;  // first of the group's 2P rows
-  const cplx<T>* in = H2 + (size_t)z * rows * g.B2 + (size_t)row0 * g.B2;
+  const cplx<T>* in = H2 + (size_t)z * rows * g.H2s + (size_t)row0 * g.H2s;
   for (int u = threadIdx.x; u < 2 * P * W; u += kFftThreads) {
     const int r = u / W, c = u - r * W;
-    raw[u] = in[(size_t)r * g.B2 + c];
+    raw[u] = in[(size_t)r * g.H2s + c];
   }
   __syncthreads();
   constexpr int E = P * N / kFftThreads;
@@ -296,11 +296,11 @@ __global__ __launch_bounds__(kFftThreads) void c2r_p3_wedge(const cplx<double>* 
   const int cm = col_max(g, qmax[geom_shell(g, z)]);
   const int W = cm + 1;
   const int r0 = blockIdx.x * 2 * P;
-  const cplx<T>* in = H2 + (size_t)z * N * N * g.B2;
+  const cplx<T>* in = H2 + (size_t)z * N * N * g.H2s;
   for (int u = threadIdx.x; u < 2 * P * W; u += kFftThreads) {
     const int r = u / W, c = u - r * W;
     const int rr = min(r0 + r, nrows - 1);  // rows past the end repeat the last one (unused)
-    rawd[u] = in[((size_t)rows[3 * rr] * N + rows[3 * rr + 1]) * g.B2 + c];
+    rawd[u] = in[((size_t)rows[3 * rr] * N + rows[3 * rr + 1]) * g.H2s + c];
   }
   __syncthreads();
   constexpr int E = P * N / kFftThreads;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ 
   }
   __syncthreads();
   fft_block<T, N, P, NS, -1>(buf, stw);
-  cplx<T>* o = H2 + (size_t)z * rows * g.B2 + (size_t)row0 * g.B2;
+  cplx<T>* o = H2 + (size_t)z * rows * g.H2s + (size_t)row0 * g.H2s;
   for (int u = threadIdx.x; u < 2 * P * g.B2; u += kFftThreads) {
     const int r = u / g.B2, c = u % g.B2;
     const int pp = r >> 1;
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q3(const float* __restrict__ 
     } else {  // B = (Z[c] - conj(Z[-c])) / (2i)
       v = cplx<T>{(T)0.5 * (Zp.im + Zm.im), (T)0.5 * (Zm.re - Zp.re)};
     }
-    o[u] = v;
+    o[(size_t)r * g.H2s + c] = v;
   }
 }
 
@@ -398,14 +398,14 @@ __global__ __launch_bounds__(kFftThreads) void r2c_q2(const cplx<float>* __restr
   if (it > 0) __syncthreads();          // the previous plane's output has left the LDS
   const int xs = blockIdx.y * reps + it;   // plane within the slab
   const int x1 = g.x1_0 + xs;
-  const cplx<T>* in = H2 + (size_t)z * N * g.S1 * g.B2;
+  const cplx<T>* in = H2 + (size_t)z * N * g.S1 * g.H2s;
   constexpr int E = P * N / kFftThreads;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int u = threadIdx.x + m * kFftThreads;
     const int pp = u % P, x0 = u / P;
     const int c = c0 + pp;
-    buf[pp * NS + pad8(x0)] = (c < g.B2) ? in[((size_t)x0 * g.S1 + xs) * g.B2 + c] : cplx<T>{0, 0};
+    buf[pp * NS + pad8(x0)] = (c < g.B2) ? in[((size_t)x0 * g.S1 + xs) * g.H2s + c] : cplx<T>{0, 0};
   }
   __syncthreads();
   fft_block<T, N, P, NS, -1>(buf, stw);

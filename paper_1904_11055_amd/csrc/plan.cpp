@@ -229,6 +229,9 @@ hipEvent_t ev_get(polyspec_plan_s* p) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Row stride of H2 (see Geom): B2 rounded up to 16 entries.
+size_t h2_stride(const polyspec_plan_s* p) { return ((size_t)p->B2 + 15) & ~(size_t)15; }
+
 // The adjoint product exists for order 3 up to 64 shells and order 4 up to 32.
 bool has_adjoint(const polyspec_plan_s* p) {
   if (p->mp) return false;
@@ -241,6 +244,7 @@ Geom make_geom(const polyspec_plan_s* p, int spb, int shell_base) {
   g.Kc = p->Kc;
   g.B0 = p->B0;
   g.B2 = p->B2;
+  g.H2s = h2_stride(p);
   g.spb = spb;
   g.shell_base = shell_base;
   g.n_shells = p->nb;
@@ -313,7 +317,7 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   L.H1 = align256(zf * p->N * p->B2 * p->B0 * sizeof(cplx<float>));
   L.H1a = (adjoint && p->streamed) ? L.H1 : 0;
   // H2 also takes the input's first transform, batch x N^2 x B2, when a slab is smaller
-  L.H2 = align256(std::max(zf * p->N * planes, (size_t)p->batch * p->N * p->N) * p->B2 * sizeof(cplx<float>));
+  L.H2 = align256(std::max(zf * p->N * planes, (size_t)p->batch * p->N * p->N) * h2_stride(p) * sizeof(cplx<float>));
   L.D = align256(zf * (size_t)p->N * planes * p->N * sizeof(float));
   L.A = (adjoint && !ps::adjoint_fuses_rows(p->N)) ? L.D : 0;   // adjoint fields only when not fused
   const size_t tiles = (size_t)std::max(p->n_tiles, p->n_tiles_j);
@@ -643,11 +647,11 @@ polyspec_status compute_counts(polyspec_plan_s* p) {
     if ((st = upload(p, &cand_d, p->cand)) != POLYSPEC_OK) break;
     if ((st = dev_alloc(p, &cw, (size_t)nb * nwedge * sizeof(double))) != POLYSPEC_OK) break;
     // shells per group: keep the float64 intermediates near 4 GiB
-    const size_t per_shell = ((size_t)N * p->B2 * p->B0 + (size_t)N * N * p->B2) * sizeof(cplx<double>);
+    const size_t per_shell = ((size_t)N * p->B2 * p->B0 + (size_t)N * N * h2_stride(p)) * sizeof(cplx<double>);
     int gs = (int)std::max<size_t>(1, std::min<size_t>(nb, ((size_t)4 << 30) / std::max<size_t>(per_shell, 1)));
     gs = std::max(1, std::min(gs, nb));
     if ((st = dev_alloc(p, &H1d, (size_t)gs * N * p->B2 * p->B0 * sizeof(cplx<double>))) != POLYSPEC_OK) break;
-    if ((st = dev_alloc(p, &H2d, (size_t)gs * N * N * p->B2 * sizeof(cplx<double>))) != POLYSPEC_OK) break;
+    if ((st = dev_alloc(p, &H2d, (size_t)gs * N * N * h2_stride(p) * sizeof(cplx<double>))) != POLYSPEC_OK) break;
     hipError_t e = hipSuccess;
     for (int s0 = 0; s0 < nb && e == hipSuccess; s0 += gs) {
       const int cnt = std::min(gs, nb - s0);
