@@ -171,11 +171,11 @@ def main():
     order = w["order"]
     if order not in (3, 4, 5, 6):
         raise SystemExit("the benchmark step needs an order-3 to order-6 workload")
-    # orders 3 (up to 64 shells) and 4 (up to 32) have the adjoint: a step is forward +
+    # orders 3 and 4 (up to 64 shells) have the adjoint: a step is forward +
     # backward; otherwise forward only
     streamed = bool(w.get("stream"))
     N, nb, width, batch = w["N"], w["n_shells"], w["width"], len(w["seeds"])
-    has_backward = (order == 3 and nb <= 64) or (order == 4 and nb <= 32)
+    has_backward = order in (3, 4) and nb <= 64
     codes = {"bf16": ps.SPLIT_BF16, "fp16": ps.SPLIT_FP16, "fp32": ps.FP32}
     prec = codes[args.precision]
     bwd_name = args.bwd_precision if args.bwd_precision != "auto" else ("fp32" if args.precision == "fp32" else "bf16")

@@ -76,7 +76,7 @@ typedef struct {
   int32_t order;        /* n = 2 to 6 (Sec. 4.2 runs the estimator up to hexagons, n = 6)  */
   int32_t n_shells;     /* N_b >= 1; (N_b + 1/2) * width <= N/2; the matrix-core contraction
                            handles N_b <= 128 at orders 2 to 4 and N_b <= 32 at orders 5 and 6;
-                           polyspec_backward needs N_b <= 64 (order 3) or N_b <= 32 (order 4)   */
+                           polyspec_backward needs N_b <= 64 (orders 3 and 4)   */
   double shell_width;   /* D > 0, in units of k_f (exact binary value is used)              */
   int32_t batch;        /* independent fields processed together, >= 1                      */
   int32_t precision;    /* polyspec_precision                                                */
@@ -123,8 +123,8 @@ polyspec_status polyspec_contract(polyspec_plan_t plan, double* d_out, double* d
  * product of the other shell fields to a_m of its shell m; g[q] = sum_m [s(q) = m]
  * R2C(a_m)[q] and dL/d delta is its unnormalised C2R.  Uses the shell fields of
  * the last polyspec_shells call; the caller must not have called polyspec_shells
- * with another input in between (the library cannot tell).  Orders 3 and 4 (order 4
- * with at most 32 shells, order 3 with at most 64); POLYSPEC_ERR_UNSUPPORTED otherwise.  The adjoint
+ * with another input in between (the library cannot tell).  Orders 3 and 4 with at
+ * most 64 shells (not multipole plans); POLYSPEC_ERR_UNSUPPORTED otherwise.  The adjoint
  * product runs in float32 for POLYSPEC_FP32 and in split precision otherwise. */
 polyspec_status polyspec_backward(polyspec_plan_t plan, const double* d_grad_out, void* d_grad_delta);
 

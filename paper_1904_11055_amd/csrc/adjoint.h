@@ -59,13 +59,20 @@ constexpr size_t adj_lds_bytes() {
   const size_t stage = (size_t)2 * kAdjStageWords * sizeof(uint4);
   return adj_fft_lds_bytes<NF>() > stage ? adj_fft_lds_bytes<NF>() : stage;
 }
-constexpr int kAdj4StageItems = 8;                                    // items (w, v) per order-4 stage
-constexpr int kAdj4StageWords = kAdj4StageItems * kAdj4WordsPerItem;
-constexpr int kAdj4Piece = kAdj4StageWords / kAdjThreads;            // words per thread per stage
-static_assert(kAdj4Piece * kAdjThreads == kAdj4StageWords, "an order-4 stage is copied in equal pieces");
-template <int NF>
+// Order 4 with NC chunks of 16 shells (2: up to 32 shells, one 32-row block of m; 4: up
+// to 64, two blocks): items (w, v) per LDS stage, operand words per stage and per thread.
+template <int NC>
+constexpr int adj4_stage_items() { return NC == 2 ? 8 : 2; }
+template <int NC>
+constexpr int adj4_stage_words() { return adj4_stage_items<NC>() * adj4_words_per_item(16 * NC); }
+template <int NC>
+constexpr int adj4_piece() { return adj4_stage_words<NC>() / kAdjThreads; }
+static_assert(adj4_piece<2>() * kAdjThreads == adj4_stage_words<2>() &&
+                  adj4_piece<4>() * kAdjThreads == adj4_stage_words<4>(),
+              "an order-4 stage is copied in equal pieces");
+template <int NF, int NC>
 constexpr size_t adj4_lds_bytes() {
-  const size_t stage = (size_t)2 * kAdj4StageWords * sizeof(uint4);   // double buffered
+  const size_t stage = (size_t)2 * adj4_stage_words<NC>() * sizeof(uint4);   // double buffered
   return adj_fft_lds_bytes<NF>() > stage ? adj_fft_lds_bytes<NF>() : stage;
 }
 
@@ -453,17 +460,18 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint_gemm(const float* __re
   adjoint_epilogue<NF>(acc, lds, lane, wave, hh, col, b, xw, n_shells, G, A, H2, tw, g);
 }
 
-// Order 4 (at most 32 shells, one 32-row block of m).  Items (w, v <= w) in order of w;
-// for each item Y = sum over the chunks uc <= v / 16 of W4_(v,w) d_u runs on the matrix
+// Order 4 (NC = 2: at most 32 shells, one 32-row block of m; NC = 4: at most 64 shells,
+// two blocks).  Items (w, v <= w) in order of w; for each item and block of m,
+// Y = sum over the chunks uc <= v / 16 of W4_(v,w) d_u runs on the matrix
 // cores with the fields themselves as the B operand, and a_m += d_v d_w Y on the VALU,
 // one float32 multiply-add per accumulator element (FP16: the scaled scalar times 2^-7,
 // the shift that the weights' row exponents carry).  Forming d_u d_v d_w for every item
 // and chunk instead cost more VALU instructions than the MFMAs could hide.  The weights
-// pass through LDS in stages of kAdj4StageItems items of one w (v in [8 c, 8 c + 8)),
+// pass through LDS in stages of adj4_stage_items items of one w (8 for NC = 2, 2 for 4),
 // double buffered: the next stage is loaded into registers while one is in use, then
 // stored, with one barrier per stage.  d_w and the item masks of the next w are likewise
 // loaded a w ahead.
-template <int PREC, int NF>
+template <int PREC, int NF, int NC>
 __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __restrict__ D,
                                                               const uint4* __restrict__ W,
                                                               const int* __restrict__ imask,
@@ -472,8 +480,13 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
                                                               int n_shells, long long G, float* __restrict__ A,
                                                               cplx<float>* __restrict__ H2,
                                                               const cplx<float>* __restrict__ tw, Geom g) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[adj4_lds_bytes<NF>()];
-  auto wst = reinterpret_cast<uint4(*)[kAdj4StageWords]>(lds);
+  constexpr int MB = NC / 2;                               // 32-row blocks of m
+  constexpr int WPI = adj4_words_per_item(16 * NC);       // operand words per item
+  constexpr int SI = adj4_stage_items<NC>();
+  constexpr int SW = adj4_stage_words<NC>();
+  constexpr int PIECE = adj4_piece<NC>();
+  __shared__ __attribute__((aligned(16))) unsigned char lds[adj4_lds_bytes<NF, NC>()];
+  auto wst = reinterpret_cast<uint4(*)[SW]>(lds);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -482,17 +495,17 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
   const long long xw = (long long)blockIdx.x * kAdjPts + wave * 32 * kAdjPB + col;
   const float* Db = D + (size_t)b * n_shells * G;
   const int n_items = n_shells * (n_shells + 1) / 2;
-  const uint4* Wb = W + (size_t)b * n_items * kAdj4WordsPerItem;
+  const uint4* Wb = W + (size_t)b * n_items * WPI;
   const int* Ib = imask;   // one mask per item, shared by the batch
 
-  AdjFields<PREC, 2> f;
-  adj_load_fields<PREC, 2>(f, Db, G, xw, hh, n_shells, absmax, b);
+  AdjFields<PREC, NC> f;
+  adj_load_fields<PREC, NC>(f, Db, G, xw, hh, n_shells, absmax, b);
   // the fields as B operands (FP16: the split operands themselves)
-  Operand<PREC> fop[kAdjPB][2];
+  Operand<PREC> fop[kAdjPB][NC];
 #pragma unroll
   for (int pb = 0; pb < kAdjPB; ++pb)
 #pragma unroll
-    for (int uc = 0; uc < 2; ++uc) {
+    for (int uc = 0; uc < NC; ++uc) {
       if constexpr (PREC == kFP16) fop[pb][uc] = f.H[pb][uc];
       else fop[pb][uc] = make_operand<PREC>(f.F[pb][uc], 1.f);
     }
@@ -504,21 +517,21 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[pb][mb][i] = 0.f;
 
-  // stage (w, c): items w (w + 1) / 2 + 8 c + k, k < 8.  Items past w are never read
+  // stage (w, c): items w (w + 1) / 2 + SI c + k, k < SI.  Items past w are never read
   // from LDS; their loads only stay in bounds (they reread the first item).
-  u32x4 wp[kAdj4Piece];
+  u32x4 wp[PIECE];
   auto s_load = [&](int w, int c) {
-    const size_t base = (size_t)(w * (w + 1) / 2 + kAdj4StageItems * c) * kAdj4WordsPerItem;
+    const size_t base = (size_t)(w * (w + 1) / 2 + SI * c) * WPI;
 #pragma unroll
-    for (int k = 0; k < kAdj4Piece; ++k) {
+    for (int k = 0; k < PIECE; ++k) {
       const int i = k * kAdjThreads + tid;
-      const bool real = kAdj4StageItems * c + i / kAdj4WordsPerItem <= w;
-      wp[k] = *reinterpret_cast<const u32x4*>(Wb + (real ? base + i : (size_t)(i % kAdj4WordsPerItem)));
+      const bool real = SI * c + i / WPI <= w;
+      wp[k] = *reinterpret_cast<const u32x4*>(Wb + (real ? base + i : (size_t)(i % WPI)));
     }
   };
   auto s_store = [&](int buf) {
 #pragma unroll
-    for (int k = 0; k < kAdj4Piece; ++k) *reinterpret_cast<u32x4*>(&wst[buf][k * kAdjThreads + tid]) = wp[k];
+    for (int k = 0; k < PIECE; ++k) *reinterpret_cast<u32x4*>(&wst[buf][k * kAdjThreads + tid]) = wp[k];
   };
   s_load(0, 0);
   s_store(0);
@@ -544,46 +557,81 @@ __global__ __launch_bounds__(kAdjThreads, 1) void adjoint4_gemm(const float* __r
       const int it1 = (w + 1) * (w + 2) / 2;
       mask_next = lane <= w + 1 ? Ib[it1 + lane] : 0;
     }
-    static_for<kAdj4MaxShells / kAdj4StageItems>([&](auto cc) {
+    static_for<16 * NC / SI>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
-      if (kAdj4StageItems * c > w) return;
+      if (SI * c > w) return;
       int nw = w, nc = c + 1;                       // the stage after this one
-      if (kAdj4StageItems * nc > w) {
+      if (SI * nc > w) {
         nw = w + 1;
         nc = 0;
       }
       const bool more = nw < n_shells;
       if (more) s_load(nw, nc);
-      static_for<kAdj4StageItems>([&](auto kc) {
+      static_for<SI>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        constexpr int v = kAdj4StageItems * c + k;
+        constexpr int v = SI * c + k;
         constexpr int vc = v / 16, vv = v % 16;
         if (v > w) return;
-        const int mask = __builtin_amdgcn_readlane(my_mask, v);   // bit uc
+        const int mask = __builtin_amdgcn_readlane(my_mask, v);   // bit 2 uc + mb
         if (!mask) return;
-        const uint4* wv = wst[buf] + k * kAdj4WordsPerItem;
-        f32x16 Y[kAdjPB];
-        static_for<vc + 1>([&](auto ucc) {
-          constexpr int uc = decltype(ucc)::value;   // no branch per chunk (zero weights where empty)
-          const Operand<PREC> Wop = op_from_words<PREC>(wv[uc * 128 + lane], wv[uc * 128 + 64 + lane]);
+        const uint4* wv = wst[buf] + k * WPI;
+        if constexpr (MB == 1) {
+          // one block of m: the chain, then the scalar and the multiply-adds
+          f32x16 Y[kAdjPB];
+          static_for<vc + 1>([&](auto ucc) {
+            constexpr int uc = decltype(ucc)::value;   // no branch per chunk (zero weights where empty)
+            const Operand<PREC> Wop = op_from_words<PREC>(wv[uc * 128 + lane], wv[uc * 128 + 64 + lane]);
+#pragma unroll
+            for (int pb = 0; pb < kAdjPB; ++pb) {
+              if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
+              else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+            }
+          });
 #pragma unroll
           for (int pb = 0; pb < kAdjPB; ++pb) {
-            if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
-            else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+            const unsigned dv = adj_scalar<PREC, NC, vc, vv>(f, pb);
+            float sv;
+            if constexpr (PREC == kFP16)
+              sv = (float)__builtin_bit_cast(_Float16, (unsigned short)(dv & 0xffffu)) +
+                   (float)__builtin_bit_cast(_Float16, (unsigned short)(dv >> 16));
+            else
+              sv = __uint_as_float(dv);
+            const float sc = sv * dw[pb];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[pb][0][i] = fmaf(sc, Y[pb][i], acc[pb][0][i]);
           }
-        });
+        } else {
+          float sc[kAdjPB];
 #pragma unroll
-        for (int pb = 0; pb < kAdjPB; ++pb) {
-          const unsigned dv = adj_scalar<PREC, 2, vc, vv>(f, pb);
-          float sv;
-          if constexpr (PREC == kFP16)
-            sv = (float)__builtin_bit_cast(_Float16, (unsigned short)(dv & 0xffffu)) +
-                 (float)__builtin_bit_cast(_Float16, (unsigned short)(dv >> 16));
-          else
-            sv = __uint_as_float(dv);
-          const float s = sv * dw[pb];
+          for (int pb = 0; pb < kAdjPB; ++pb) {
+            const unsigned dv = adj_scalar<PREC, NC, vc, vv>(f, pb);
+            float sv;
+            if constexpr (PREC == kFP16)
+              sv = (float)__builtin_bit_cast(_Float16, (unsigned short)(dv & 0xffffu)) +
+                   (float)__builtin_bit_cast(_Float16, (unsigned short)(dv >> 16));
+            else
+              sv = __uint_as_float(dv);
+            sc[pb] = sv * dw[pb];
+          }
 #pragma unroll
-          for (int i = 0; i < 16; ++i) acc[pb][0][i] = fmaf(s, Y[pb][i], acc[pb][0][i]);
+          for (int mb = 0; mb < MB; ++mb) {
+            if (!(mask & (0x55 << mb))) continue;   // no weight in this block of m
+            f32x16 Y[kAdjPB];
+            static_for<vc + 1>([&](auto ucc) {
+              constexpr int uc = decltype(ucc)::value;
+              const uint4* wb = wv + (uc * MB + mb) * 128;
+              const Operand<PREC> Wop = op_from_words<PREC>(wb[lane], wb[64 + lane]);
+#pragma unroll
+              for (int pb = 0; pb < kAdjPB; ++pb) {
+                if constexpr (uc == 0) adj_mma_first<PREC>(Y[pb], Wop, fop[pb][uc]);
+                else adj_mma<PREC>(Y[pb], Wop, fop[pb][uc]);
+              }
+            });
+#pragma unroll
+            for (int pb = 0; pb < kAdjPB; ++pb)
+#pragma unroll
+              for (int i = 0; i < 16; ++i) acc[pb][mb][i] = fmaf(sc[pb], Y[pb][i], acc[pb][mb][i]);
+          }
         }
       });
       if (more) s_store(buf ^ 1);
@@ -621,8 +669,13 @@ hipError_t launch_adjoint4_gemm_prec(const float* D, const uint4* W, const int* 
                                      const unsigned long long* rowmax, int n_shells, long long G, float* A,
                                      cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st) {
   dim3 grid((unsigned)(G / kAdjPts), batch);
-#define L(NF) hipLaunchKernelGGL((adjoint4_gemm<PREC, NF>), grid, dim3(kAdjThreads), 0, st, D, W, imask, absmax, \
-                                 rowmax, n_shells, G, A, H2, tw, g)
+#define L4(NF, NC) hipLaunchKernelGGL((adjoint4_gemm<PREC, NF, NC>), grid, dim3(kAdjThreads), 0, st, D, W, imask, \
+                                      absmax, rowmax, n_shells, G, A, H2, tw, g)
+#define L(NF)                      \
+  do {                             \
+    if (n_shells <= 32) L4(NF, 2); \
+    else L4(NF, 4);                \
+  } while (0)
   switch (g.N) {
     case 32: L(32); break;
     case 64: L(64); break;
@@ -632,6 +685,7 @@ hipError_t launch_adjoint4_gemm_prec(const float* D, const uint4* W, const int* 
     default: L(0); break;
   }
 #undef L
+#undef L4
   return hipGetLastError();
 }
 

@@ -142,9 +142,10 @@ __global__ void adjoint_weights(const double* __restrict__ grad, const double* _
   adj_store_weight(base, ln, r, w, prec);
 }
 
-// Order 4: W4[b][item (w, v <= w)][uc][hi, lo][lane]: lane l holds row m = l % 32 and
-// u = 16 uc + 8 (l / 32) + r (zero when u > v).  FP16: scaled by 2^(e_m + 7 - sigma_u -
-// sigma_v - sigma_w).  grid (32: u, items, batch), threads m.
+// Order 4: W4[b][item (w, v <= w)][uc][mb][hi, lo][lane] (NC chunks of u, NC / 2 blocks
+// of m: adj4_chunks): lane l holds row m = 32 mb + l % 32 and u = 16 uc + 8 (l / 32) + r
+// (zero when u > v).  FP16: scaled by 2^(e_m + 7 - sigma_u - sigma_v - sigma_w).
+// grid (16 NC: u, items, batch), threads m (16 NC).
 __global__ void adjoint4_weights(const double* __restrict__ grad, const double* __restrict__ fnorm,
                                  const int* __restrict__ lookup, int n_shells, int n_closing, int prec,
                                  const unsigned* __restrict__ absmax, const unsigned long long* __restrict__ rowmax,
@@ -161,9 +162,10 @@ __global__ void adjoint4_weights(const double* __restrict__ grad, const double* 
       val = ldexp(val, adj_row_exp(rowmax, b * 64 + m) + adj_weight_exp<4>(absmax, b, n_shells, rest));
   }
   const int n_items = n_shells * (n_shells + 1) / 2;
+  const int nc = adj4_chunks(n_shells), nm = nc / 2;
   const int uc = u >> 4, q = u & 15, hh = q >> 3, r = q & 7;
-  const int ln = 32 * hh + m;
-  uint4* base = W + (((size_t)b * n_items + it) * 2 + uc) * 2 * 64;
+  const int ln = 32 * hh + (m & 31), mb = m >> 5;
+  uint4* base = W + ((((size_t)b * n_items + it) * nc + uc) * nm + mb) * 2 * 64;
   adj_store_weight(base, ln, r, val, prec);
 }
 
@@ -190,13 +192,14 @@ hipError_t launch_adjoint4_weights(const double* grad, const double* fnorm, cons
                                    uint4* W, int batch, hipStream_t st) {
   if (n_shells > kAdj4MaxShells) return hipErrorInvalidValue;
   const int n_items = n_shells * (n_shells + 1) / 2;
+  const int nu = 16 * adj4_chunks(n_shells);   // values of u (and of m) the operand words cover
   if (prec == kFP16) {
     hipError_t e = launch_fill_u32(rowmax, 0u, (size_t)batch * 64 * 2, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(adjoint4_rowmax, dim3(n_items, batch), dim3(32), 0, st, grad, fnorm, lookup, n_shells,
+    hipLaunchKernelGGL(adjoint4_rowmax, dim3(n_items, batch), dim3(nu), 0, st, grad, fnorm, lookup, n_shells,
                        n_closing, absmax, rowmax);
   }
-  hipLaunchKernelGGL(adjoint4_weights, dim3(32, n_items, batch), dim3(32), 0, st, grad, fnorm, lookup, n_shells,
+  hipLaunchKernelGGL(adjoint4_weights, dim3(nu, n_items, batch), dim3(nu), 0, st, grad, fnorm, lookup, n_shells,
                      n_closing, prec, absmax, rowmax, W);
   return hipGetLastError();
 }

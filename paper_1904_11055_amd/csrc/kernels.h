@@ -122,10 +122,15 @@ inline bool adjoint_fuses_rows(int N) { return N <= 512; }
 hipError_t launch_adjoint_gemm(int prec, const float* D, const uint4* W, const int* vmask, const unsigned* absmax,
                                const unsigned long long* rowmax, int n_shells, long long G, float* A,
                                cplx<float>* H2, const cplx<float>* tw, Geom g, int batch, hipStream_t st);
-// Order 4 (n_shells <= kAdj4MaxShells): W4[b][item (w, v <= w)][uc][hi, lo][lane], item = w (w + 1) / 2 + v.
-constexpr int kAdj4MaxShells = 32;
+// Order 4 (n_shells <= kAdj4MaxShells): W4[b][item (w, v <= w)][uc][mb][hi, lo][lane],
+// item = w (w + 1) / 2 + v, over NC = 2 chunks of u and one 32-row block of m up to 32
+// shells, NC = 4 chunks and two blocks above.
+constexpr int kAdj4MaxShells = 64;
 constexpr int kAdj3MaxShells = 64;
-constexpr int kAdj4WordsPerItem = 2 * 2 * 64;
+__host__ __device__ constexpr int adj4_chunks(int n_shells) { return n_shells <= 32 ? 2 : 4; }
+__host__ __device__ constexpr int adj4_words_per_item(int n_shells) {
+  return adj4_chunks(n_shells) * (adj4_chunks(n_shells) / 2) * 2 * 64;
+}
 hipError_t launch_adjoint4_weights(const double* grad, const double* fnorm, const int* lookup, int n_shells,
                                    int n_closing, int prec, const unsigned* absmax, unsigned long long* rowmax,
                                    uint4* W, int batch, hipStream_t st);

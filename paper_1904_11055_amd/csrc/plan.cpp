@@ -232,7 +232,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Row stride of H2 (see Geom): B2 rounded up to 16 entries.
 size_t h2_stride(const polyspec_plan_s* p) { return ((size_t)p->B2 + 15) & ~(size_t)15; }
 
-// The adjoint product exists for order 3 up to 64 shells and order 4 up to 32.
+// The adjoint product exists for orders 3 and 4 up to 64 shells.
 bool has_adjoint(const polyspec_plan_s* p) {
   if (p->mp) return false;
   return (p->order == 3 && p->nb <= ps::kAdj3MaxShells) || (p->order == 4 && p->nb <= ps::kAdj4MaxShells);
@@ -326,7 +326,7 @@ WsLayout layout_of(const polyspec_plan_s* p) {
   L.absmax = align256(zf * sizeof(unsigned)) + align256(zf * ps::kAbsmaxSpreadHost * sizeof(unsigned));
   L.W = !adjoint ? 0
         : p->order == 3 ? align256((size_t)p->batch * p->nb * 4 * 2 * 2 * 64 * 16)
-        : adjoint ? align256((size_t)p->batch * (p->nb * (p->nb + 1) / 2) * ps::kAdj4WordsPerItem * 16)
+        : adjoint ? align256((size_t)p->batch * (p->nb * (p->nb + 1) / 2) * ps::adj4_words_per_item(p->nb) * 16)
                   : 0;
   L.rowmax = adjoint ? align256((size_t)p->batch * 64 * sizeof(unsigned long long)) : 0;
   L.total = L.box + L.gbox + L.H1 + L.H1a + L.H2 + L.D + L.A + L.partials + L.red + L.absmax + L.W + L.rowmax;
@@ -943,19 +943,21 @@ polyspec_status build_plan(polyspec_plan_s* p) {
   }
   if (adj4) {
     PS_TRY(upload(p, &p->lookup_d, lookup));
-    // for each item (w, v <= w): which 16-shell chunks uc of u <= v hold a weight
-    // W4[m][(u, v, w)] (bit uc); the order-4 adjoint skips items without any
+    // for each item (w, v <= w): which (16-shell chunk uc of u <= v, 32-row block mb of
+    // m) hold a weight W4[m][(u, v, w)] (bit 2 uc + mb): each closing tuple, with each of
+    // its positions taken by m and the other three (u <= v <= w); the order-4 adjoint
+    // skips items without any, and blocks of m without any
     const int nb = p->nb;
     std::vector<int> imask(nb * (nb + 1) / 2, 0);
-    for (int w = 0; w < nb; ++w)
-      for (int v = 0; v <= w; ++v)
-        for (int u = 0; u <= v; ++u)
-          for (int m = 0; m < nb; ++m) {
-            int t[4] = {m, u, v, w};
-            std::sort(t, t + 4);
-            if (lookup[(((size_t)t[0] * nb + t[1]) * nb + t[2]) * nb + t[3]] >= 0)
-              imask[w * (w + 1) / 2 + v] |= 1 << (u / 16);
-          }
+    for (size_t k = 0; k < p->closing.size(); ++k) {
+      const int* t = &p->cl_bins[k * 4];
+      for (int pos = 0; pos < 4; ++pos) {
+        int rest[3], r = 0;
+        for (int j = 0; j < 4; ++j)
+          if (j != pos) rest[r++] = t[j];
+        imask[rest[2] * (rest[2] + 1) / 2 + rest[1]] |= 1 << (2 * (rest[0] / 16) + t[pos] / 32);
+      }
+    }
     p->wmask_host = imask;
     PS_TRY(upload(p, &p->wmask_d, imask));
   }
@@ -1315,7 +1317,7 @@ polyspec_status polyspec_backward(polyspec_plan_t p, const double* d_grad_out, v
   if (!p) return POLYSPEC_ERR_INVALID_ARG;
   if (!has_adjoint(p))
     return p->fail(POLYSPEC_ERR_UNSUPPORTED,
-                   "backward is implemented for order 3 with at most 64 shells and order 4 with at most 32 "
+                   "backward is implemented for orders 3 and 4 with at most 64 shells "
                    "(not for multipole plans)");
   if (!d_grad_out || !d_grad_delta) return p->fail(POLYSPEC_ERR_INVALID_ARG, "null pointer");
   if (!p->have_fields) return p->fail(POLYSPEC_ERR_STATE, "polyspec_backward before polyspec_shells");
@@ -1471,19 +1473,35 @@ polyspec_status polyspec_issued_flops(polyspec_plan_t p, int32_t phase, double* 
     const bool aligned = p->jsched && p->prec == POLYSPEC_SPLIT_FP16 && p->ksteps_j % 4 == 0;
     *flops = (aligned ? p->n_tiles_j : p->n_tiles) * 512.0 * terms * pts;
   } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 4 && p->nb <= ps::kAdj4MaxShells) {
-    // per item (w, v): the 16-shell chunks of u <= v, one 32-row block of m
+    // per item (w, v): the 16-shell chunks of u <= v, for each 32-row block of m with a
+    // weight (the only block up to 32 shells)
     double blocks = 0.0;
+    const int mbn = p->nb > 32 ? 2 : 1;
     for (int w = 0; w < p->nb; ++w)
-      for (int v = 0; v <= w; ++v)
-        if (p->wmask_host[w * (w + 1) / 2 + v]) blocks += v / 16 + 1;
+      for (int v = 0; v <= w; ++v) {
+        const int mask = p->wmask_host[w * (w + 1) / 2 + v];
+        if (!mask) continue;
+        for (int mb = 0; mb < mbn; ++mb)
+          if (mbn == 1 || (mask & (0x55 << mb))) blocks += v / 16 + 1;
+      }
     *flops = blocks * 32.0 * 32.0 * 16.0 * 2.0 / 32.0 * terms * pts;
   } else if (phase == POLYSPEC_PH_ADJ_GEMM && p->order == 3 && has_adjoint(p)) {
-    // per partner shell v: the 32-row blocks of m with a weight, each times the
-    // 16-shell chunks of u <= v, as 32 x 32 x 16 products per 32 grid points
+    // per partner shell v, 32 x 32 x 16 products per 32 grid points: for v >= 16 in FP32
+    // and BF16 every (16-shell chunk u <= v, 32-row block of m); otherwise the blocks
+    // that hold a weight (the adjoint's arithmetic is that of backward())
+    const bool fp16 = p->prec == POLYSPEC_SPLIT_FP16 && !p->streamed;
+    const int mbn = p->nb > 32 ? 2 : 1;
     double blocks = 0.0;
-    for (int v = 0; v < p->nb; ++v)
-      for (int mb = 0; mb < 2; ++mb)
-        if (p->wmask_host[v] & (0x55 << mb)) blocks += v / 16 + 1;
+    for (int v = 0; v < p->nb; ++v) {
+      const int mask = p->wmask_host[v];
+      if (!mask) continue;
+      if (!fp16 && v >= 16) {
+        blocks += mbn * (v / 16 + 1);
+        continue;
+      }
+      for (int mb = 0; mb < mbn; ++mb)
+        for (int uc = 0; uc <= v / 16; ++uc) blocks += (mask >> (2 * uc + mb)) & 1;
+    }
     *flops = blocks * 32.0 * 32.0 * 16.0 * 2.0 / 32.0 * terms * pts;
   }
   return POLYSPEC_OK;

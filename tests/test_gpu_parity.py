@@ -423,15 +423,44 @@ def test_trispectrum_gradient_matches_oracle(gpu, precision, tol, N, nb, width, 
     plan.close()
 
 
-def test_trispectrum_backward_limits(gpu):
-    """More than 32 shells: the order-4 backward reports UNSUPPORTED, the forward still works."""
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,tol", [(0, 1e-4), (1, 1e-4), (2, 1e-4)])
+def test_trispectrum_gradient_more_than_32_shells(gpu, precision, tol):
+    """34 shells of width 1/4 at 64^3 (alias-free: 4 x 34.5 / 4 <= 64; the thinnest shells
+    hold no mode): the order-4 adjoint with four 16-shell chunks of u and two 32-row blocks
+    of m (a ragged last block of each), against the FP64 oracle gradient."""
     import torch
     ps = _ps()
-    plan = ps.Plan(128, 4, 33, 1.0, flags=ps.ALLOW_ALIASING, device="cuda:0")
-    plan.shells(torch.from_numpy(fieldgen.gaussian_field(128, 3).astype(np.float32))[None].to("cuda:0"))
-    B = plan.contract()
+    N, nb, width = 64, 34, 0.25
+    key = ("tri_grad_34",)
+    if key not in _CACHE:
+        delta = fieldgen.lognormal_field(N, 52).astype(np.float32)
+        ref = O.polyspectrum(delta.astype(np.float64), 4, nb, width, return_fields=True)
+        g = np.random.default_rng(2).standard_normal(len(ref["B"]))
+        gref = O.gradient(delta.astype(np.float64), 4, nb, width, g, result=ref)
+        _CACHE[key] = (delta, ref["counts"], g, gref)
+    delta, counts, g, gref = _CACHE[key]
+    plan = ps.Plan(N, 4, nb, width, precision=precision, device="cuda:0")
+    x = torch.from_numpy(delta)[None].to("cuda:0").requires_grad_(True)
+    B = ps.polyspectrum(x, plan)
+    assert np.array_equal(plan.counts, counts)
+    B.backward(torch.from_numpy(g)[None].to("cuda:0"))
+    err = _rel(x.grad.cpu().numpy()[0], gref)
+    from conftest import PRECISION_NAMES, record_error
+    record_error("64^3 trispectrum, 34 shells of width 1/4 (lognormal): gradient of sum g_t B_t",
+                 PRECISION_NAMES[precision], grad_rel_l2=err)
+    assert err < tol
+    plan.close()
+
+
+def test_trispectrum_backward_limits(gpu):
+    """More than 64 shells: the order-4 backward reports UNSUPPORTED (the plan is refused
+    before any field is needed)."""
+    import torch
+    ps = _ps()
+    plan = ps.Plan(128, 4, 65, 0.5, flags=ps.ALLOW_ALIASING, device="cuda:0")
     with pytest.raises(ps.PolyspecError) as e:
-        plan.backward(torch.ones_like(B))
+        plan.backward(torch.ones(1, plan.n_closing, dtype=torch.float64, device="cuda:0"))
     assert e.value.status == 7
     plan.close()
 
