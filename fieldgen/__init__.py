@@ -119,6 +119,10 @@ WORKLOADS = {
                                  field="lognormal", seeds=[2]),
     "trispec_256_lognormal": dict(N=256, order=4, n_shells=24, width=2.0, batch=1,
                                   field="lognormal", seeds=[2]),
+    # the trispectrum with more than 32 shells (alias-free: 4 x 40.5 <= 256), whose adjoint
+    # takes four 16-shell chunks of u and two 32-row blocks of m
+    "trispec_256_40": dict(N=256, order=4, n_shells=40, width=1.0, batch=1,
+                           field="lognormal", seeds=[2]),
     "bispec_grad_128x8": dict(N=128, order=3, n_shells=24, width=1.0, batch=8,
                               field="gaussian", seeds=list(range(40, 48)), target_seed=48),
     "bispec_512_lognormal": dict(N=512, order=3, n_shells=64, width=1.0, batch=1,
