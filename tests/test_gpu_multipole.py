@@ -167,3 +167,22 @@ def test_multipole_batch_half_spectrum_and_box_length(gpu, precision, tol):
         assert np.array_equal(plan.tuples, ref["tuples"])
         assert _rel(B[i], ref["B"]) < tol, i
     plan.close()
+
+
+def test_multipole_allocation_free_forward(gpu):
+    """polyspec_forward_static on a multipole plan (the weighted fields made in the static
+    scratch) gives the ordinary entry points' result bit for bit."""
+    import torch
+    ps = _ps()
+    delta = fieldgen.lognormal_field(32, 76).astype(np.float32)
+    x = torch.from_numpy(delta)[None].to("cuda:0")
+    plan = ps.Plan(32, 3, 6, 1.0, precision=ps.SPLIT_FP16, multipole=2, device="cuda:0")
+    plan.shells(x)
+    B, S = (a.cpu().numpy() for a in plan.contract(raw=True))
+    assert ps.polyspec_workspace_size(plan.handle) <= ps.STATIC_SCRATCH_BYTES
+    out = torch.empty((1, plan.n_closing), dtype=torch.float64, device="cuda:0")
+    raw = torch.empty_like(out)
+    ps.polyspec_forward_static(plan.handle, x.data_ptr(), out.data_ptr(), raw.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), B) and np.array_equal(raw.cpu().numpy(), S)
+    plan.close()
