@@ -137,6 +137,8 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
   }
   // PLDS: the slots' pair blocks (uniform) and the pairs this lane forms each K-step
   constexpr int kForm = PLDS ? (2 * kMaxPairBlocks + kCtrWaves - 1) / kCtrWaves : 1;
+  // pair blocks formed per K-step: all of the plan's, or the tile group's own
+  const int n_local = PLDS ? (p.grp_nblk ? p.grp_nblk[group] : p.n_pair_blocks) : 0;
   int blk[PLDS ? NS : 1];
   int fuv[kForm];
   if constexpr (PLDS) {
@@ -146,7 +148,9 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
 #pragma unroll
     for (int f = 0; f < kForm; ++f) {
       const int t = wave + f * kCtrWaves;           // (pair block t / 2, half t % 2)
-      const int w = t < 2 * p.n_pair_blocks ? p.pair_uv[16 * (t >> 1) + row] : 0;
+      int gb = t >> 1;                              // the block's global id
+      if (p.grp_blk) gb = t < 2 * n_local ? p.grp_blk[group * kMaxPairBlocks + (t >> 1)] : 0;
+      const int w = t < 2 * n_local ? p.pair_uv[16 * gb + row] : 0;
       fuv[f] = (w & 0xff) | (((w >> 16) & 0xff) << 8);
     }
   }
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(kCtrThreads, 1) void contract_tiles(CtrParams p) {
 #pragma unroll
       for (int f = 0; f < kForm; ++f) {
         const int t = wave + f * kCtrWaves;
-        if (t < 2 * p.n_pair_blocks) {
+        if (t < 2 * n_local) {
           const Operand<kFP16> o = form_pair_f16(opHi[cur][t & 1], opLo[cur][t & 1], fuv[f], lane);
           pair_word(t & 1, t >> 1, 0) = __builtin_bit_cast(uint4, o.hi);
           pair_word(t & 1, t >> 1, 1) = __builtin_bit_cast(uint4, o.lo);

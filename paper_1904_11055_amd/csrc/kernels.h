@@ -52,6 +52,8 @@ struct CtrParams {
   int ksteps;
   int n_chunks;
   int n_pair_blocks;       // order 4, FP16: pair operands formed once per K-step in LDS (0: per slot)
+  const int* grp_blk;      // or null: [n_groups][kMaxPairBlocksHost] the group's own pair blocks (global ids)
+  const int* grp_nblk;     // [n_groups]: how many (then slot_blk holds indices into that list)
 };
 // Order 4, split FP16: pair blocks that fit the workgroup's LDS as shared operands
 // beside the staged shell operands (28 blocks of 16 pairs: up to 29 shells).

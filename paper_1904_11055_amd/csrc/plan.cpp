@@ -115,6 +115,10 @@ struct polyspec_plan_s {
   DevBuf tw32, shell_q, qmax_d, pairs_d, slots_d, slot_lane_d, slot_tile_d, slot_blk_d, ent_d, bins_d, fnorm_d, lookup_d,
       wmask_d, flag_d;
   DevBuf jtile_d, jmask_d, ent_j_d;
+  // order 4 with more pair blocks than one workgroup's LDS holds: each tile group's own
+  // pair blocks (global ids, kMaxPairBlocksHost per group) and their count
+  bool pair_groups = false;
+  DevBuf grp_blk_d, grp_nblk_d;
   DevBuf closing_of_ent_d, closing_of_ent_j_d;   // streamed plans: tile entry -> closing tuple (or -1)
   // workspace carving
   DevBuf own_ws;
@@ -502,31 +506,77 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
     for (int f = t; f < u; f += cap) units.push_back({f, std::min(cap, u - f)});
     t = u;
   }
-  // greedy: largest units first, onto the least loaded wave with room
-  std::vector<int> order(units.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return units[x].second > units[y].second; });
   struct Wave {
     std::vector<int> tiles;
     double load = 0;
   };
   std::vector<std::vector<Wave>> groups;
   auto new_group = [&]() { groups.emplace_back(ps::kCtrWavesHost); };
-  new_group();
-  for (int ui : order) {
-    const int cnt = units[ui].second;
-    if (cnt > cap) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "tile unit larger than a wave");
-    Wave* best = nullptr;
-    for (auto& grp : groups)
-      for (auto& w : grp)
-        if ((int)w.tiles.size() + cnt <= cap && (!best || w.load < best->load)) best = &w;
-    if (!best) {
-      new_group();
-      best = &groups.back()[0];
+  // Order 4 in split FP16 with more pair blocks than fit one workgroup's LDS as shared
+  // operands: tile groups over rectangles of ka A blocks by kb B blocks (ka + kb within the
+  // LDS), the rectangle sizes that give the fewest groups; each group then forms only its
+  // own blocks, once per K-step.  Tiles go to the waves in (A, B) order, a contiguous run
+  // each.  The grouping follows the precision the plan is made with: the FP32 and BF16
+  // contractions, which form pair products per tile, run faster on the greedy groups
+  // below (40 shells at 256^3, FP32: 77 against 83 ms); after a switch of precision the
+  // plan keeps its grouping (a plan made in FP32 then contracts FP16 without the sharing).
+  const int npb = p->n_pairs_padded / 16;
+  const int lmax = ps::kMaxPairBlocksHost;
+  p->pair_groups = n == 4 && p->prec == POLYSPEC_SPLIT_FP16 && p->n_blk <= 4 && npb > lmax;
+  std::vector<int> grp_blk, grp_nblk;
+  if (p->pair_groups) {
+    int best = -1, bka = 0, bkb = 0;
+    for (int ka = 1; ka < lmax; ++ka)
+      for (int kb = 1; ka + kb <= lmax; ++kb) {
+        std::map<std::pair<int, int>, int> cnt;
+        for (const TileKey& k : tlist) ++cnt[{k.a / ka, k.b / kb}];
+        int ng = 0;
+        for (const auto& kv : cnt) ng += (kv.second + 16 * cap - 1) / (16 * cap);
+        if (best < 0 || ng < best) { best = ng; bka = ka; bkb = kb; }
+      }
+    std::map<std::pair<int, int>, std::vector<int>> rect;   // tiles in (A, B) order
+    for (int t = 0; t < id; ++t) rect[{tlist[t].a / bka, tlist[t].b / bkb}].push_back(t);
+    for (const auto& kv : rect) {
+      const std::vector<int>& tl = kv.second;
+      for (size_t f = 0; f < tl.size(); f += 16 * cap) {
+        const int cnt = (int)std::min(tl.size() - f, (size_t)16 * cap);
+        new_group();
+        const int per = (cnt + ps::kCtrWavesHost - 1) / ps::kCtrWavesHost;
+        for (int k = 0; k < cnt; ++k) groups.back()[k / per].tiles.push_back(tl[f + k]);
+        std::vector<int> blocks;
+        for (int k = 0; k < cnt; ++k) {
+          blocks.push_back(tlist[tl[f + k]].a);
+          blocks.push_back(tlist[tl[f + k]].b);
+        }
+        std::sort(blocks.begin(), blocks.end());
+        blocks.erase(std::unique(blocks.begin(), blocks.end()), blocks.end());
+        if ((int)blocks.size() > lmax) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "tile group exceeds its pair blocks");
+        grp_nblk.push_back((int)blocks.size());
+        blocks.resize(lmax, -1);
+        grp_blk.insert(grp_blk.end(), blocks.begin(), blocks.end());
+      }
     }
-    for (int k = 0; k < cnt; ++k) best->tiles.push_back(units[ui].first + k);
-    best->load += 1.0 + cnt * (n >= 5 ? 3.0 : n == 4 ? 2.0 : 1.0);   // one A formation + the tiles
+  } else {
+    // greedy: largest units first, onto the least loaded wave with room
+    std::vector<int> order(units.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return units[x].second > units[y].second; });
+    new_group();
+    for (int ui : order) {
+      const int cnt = units[ui].second;
+      if (cnt > cap) return p->fail(POLYSPEC_ERR_UNSUPPORTED, "tile unit larger than a wave");
+      Wave* best = nullptr;
+      for (auto& grp : groups)
+        for (auto& w : grp)
+          if ((int)w.tiles.size() + cnt <= cap && (!best || w.load < best->load)) best = &w;
+      if (!best) {
+        new_group();
+        best = &groups.back()[0];
+      }
+      for (int k = 0; k < cnt; ++k) best->tiles.push_back(units[ui].first + k);
+      best->load += 1.0 + cnt * (n >= 5 ? 3.0 : n == 4 ? 2.0 : 1.0);   // one A formation + the tiles
+    }
   }
   p->n_groups = (int)groups.size();
   // slot tables (see contract_tiles): a uniform byte per slot and per-lane pair shells,
@@ -558,7 +608,13 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
           prev_a = k.a;
           info = (n >= 4 ? 0 : (k.b & 7)) | (n == 2 ? (k.a & 7) << 3 : 0) | (form << 6);
           slot_tile[gw * S + s] = tl[s];
-          slot_blk[gw * S + s] = k.a | (k.b << 16);
+          if (p->pair_groups) {   // the group's local block indices
+            const int* gb = &grp_blk[(size_t)gi * lmax];
+            const int la = (int)(std::find(gb, gb + lmax, k.a) - gb), lb = (int)(std::find(gb, gb + lmax, k.b) - gb);
+            slot_blk[gw * S + s] = la | (lb << 16);
+          } else {
+            slot_blk[gw * S + s] = k.a | (k.b << 16);
+          }
           for (int r = 0; r < 16; ++r) {
             int* row_words = &lanew[(gw * 16 + r) * S];
             if (n == 3) row_words[s / 2] |= uv8(16 * k.a + r) << (16 * (s % 2));
@@ -577,6 +633,10 @@ polyspec_status build_tiles(polyspec_plan_s* p, std::vector<int>* ent_of_cand) {
   PS_TRY(upload(p, &p->slot_tile_d, slot_tile));
   PS_TRY(upload(p, &p->slot_blk_d, slot_blk));
   PS_TRY(upload(p, &p->pairs_d, p->pair_uv));
+  if (p->pair_groups) {
+    PS_TRY(upload(p, &p->grp_blk_d, grp_blk));
+    PS_TRY(upload(p, &p->grp_nblk_d, grp_nblk));
+  }
   return POLYSPEC_OK;
 }
 
@@ -974,7 +1034,8 @@ void release(polyspec_plan_s* p) {
   p->ev_pool.clear();
   DevBuf* bufs[] = {&p->tw32, &p->shell_q, &p->qmax_d, &p->pairs_d, &p->slots_d, &p->slot_lane_d, &p->slot_tile_d, &p->slot_blk_d, &p->ent_d,
                     &p->bins_d, &p->fnorm_d, &p->lookup_d, &p->wmask_d, &p->flag_d, &p->jtile_d, &p->jmask_d,
-                    &p->ent_j_d, &p->closing_of_ent_d, &p->closing_of_ent_j_d, &p->own_ws};
+                    &p->ent_j_d, &p->closing_of_ent_d, &p->closing_of_ent_j_d, &p->grp_blk_d, &p->grp_nblk_d,
+                    &p->own_ws};
   for (DevBuf* b : bufs) dev_free(b);
 }
 
@@ -1197,9 +1258,12 @@ static polyspec_status contract_launch(polyspec_plan_t p, bool accumulate, long 
     cp.ksteps = p->ksteps;
     cp.n_chunks = p->n_chunks;
     // order 4 in split FP16: every pair operand formed once per K-step, shared through LDS
+    // (with more pair blocks than fit, each tile group's own blocks)
     const int npb = p->n_pairs_padded / 16;
-    cp.n_pair_blocks = (p->order == 4 && p->prec == POLYSPEC_SPLIT_FP16 && p->n_blk <= 4 && npb <= ps::kMaxPairBlocksHost)
-                           ? npb : 0;
+    const bool plds = p->order == 4 && p->prec == POLYSPEC_SPLIT_FP16 && p->n_blk <= 4;
+    cp.n_pair_blocks = !plds ? 0 : p->pair_groups ? ps::kMaxPairBlocksHost : npb;
+    cp.grp_blk = plds && p->pair_groups ? (const int*)p->grp_blk_d.p : nullptr;
+    cp.grp_nblk = plds && p->pair_groups ? (const int*)p->grp_nblk_d.p : nullptr;
     PS_TIMED(p, POLYSPEC_PH_CONTRACT, ps::launch_contract(p->prec, p->order, cp, p->n_groups, p->batch, st));
     *n_ent = (long long)p->n_tiles * 256;
     n_chunks = p->n_chunks;

@@ -428,7 +428,7 @@ def test_trispectrum_gradient_matches_oracle(gpu, precision, tol, N, nb, width, 
 def test_trispectrum_gradient_more_than_32_shells(gpu, precision, tol):
     """34 shells of width 1/4 at 64^3 (alias-free: 4 x 34.5 / 4 <= 64; the thinnest shells
     hold no mode): the order-4 adjoint with four 16-shell chunks of u and two 32-row blocks
-    of m (a ragged last block of each), against the FP64 oracle gradient."""
+    of m (a ragged last block of each), against the FP64 oracle gradient, and the forward."""
     import torch
     ps = _ps()
     N, nb, width = 64, 34, 0.25
@@ -438,12 +438,19 @@ def test_trispectrum_gradient_more_than_32_shells(gpu, precision, tol):
         ref = O.polyspectrum(delta.astype(np.float64), 4, nb, width, return_fields=True)
         g = np.random.default_rng(2).standard_normal(len(ref["B"]))
         gref = O.gradient(delta.astype(np.float64), 4, nb, width, g, result=ref)
-        _CACHE[key] = (delta, ref["counts"], g, gref)
-    delta, counts, g, gref = _CACHE[key]
+        _CACHE[key] = (delta, ref["counts"], ref["B"], g, gref)
+    delta, counts, Bref, g, gref = _CACHE[key]
     plan = ps.Plan(N, 4, nb, width, precision=precision, device="cuda:0")
     x = torch.from_numpy(delta)[None].to("cuda:0").requires_grad_(True)
     B = ps.polyspectrum(x, plan)
     assert np.array_equal(plan.counts, counts)
+    # the forward too: 38 pair blocks, more than one workgroup's LDS holds as shared
+    # operands, so the tiles run in groups that each form their own blocks
+    assert _rel(B.detach().cpu().numpy()[0], Bref) < (1e-5 if precision == 0 else 1e-4)
+    if precision == 2:   # the plan keeps its FP16 tile groups when switched to FP32
+        plan.precision = ps.FP32
+        assert _rel(plan.contract().cpu().numpy()[0], Bref) < 1e-5
+        plan.precision = ps.SPLIT_FP16
     B.backward(torch.from_numpy(g)[None].to("cuda:0"))
     err = _rel(x.grad.cpu().numpy()[0], gref)
     from conftest import PRECISION_NAMES, record_error
