@@ -460,6 +460,36 @@ def test_trispectrum_gradient_more_than_32_shells(gpu, precision, tol):
     plan.close()
 
 
+@pytest.mark.timeout(600)
+def test_trispectrum_gradient_more_than_32_shells_streamed(gpu):
+    """The 34-shell order-4 plan above run slab by slab (8 slabs of 8 planes, FP32): the
+    64-shell adjoint form writing its fields for the slab's own transforms, against the
+    FP64 oracle gradient and the resident plan."""
+    import torch
+    ps = _ps()
+    N, nb, width = 64, 34, 0.25
+    key = ("tri_grad_34",)
+    if key not in _CACHE:
+        delta = fieldgen.lognormal_field(N, 52).astype(np.float32)
+        ref = O.polyspectrum(delta.astype(np.float64), 4, nb, width, return_fields=True)
+        g = np.random.default_rng(2).standard_normal(len(ref["B"]))
+        gref = O.gradient(delta.astype(np.float64), 4, nb, width, g, result=ref)
+        _CACHE[key] = (delta, ref["counts"], ref["B"], g, gref)
+    delta, counts, Bref, g, gref = _CACHE[key]
+    x = torch.from_numpy(delta)[None].to("cuda:0")
+    out = {}
+    for flags, kw in ((ps.STREAM_SLABS, dict(slab_planes=8)), (0, {})):
+        plan = ps.Plan(N, 4, nb, width, flags=flags, device="cuda:0", **kw)
+        plan.shells(x)
+        B = plan.contract().cpu().numpy()[0]
+        assert np.array_equal(plan.counts, counts)
+        assert _rel(B, Bref) < 1e-5
+        out[flags] = plan.backward(torch.from_numpy(g)[None].to("cuda:0")).cpu().numpy()[0]
+        plan.close()
+    assert _rel(out[ps.STREAM_SLABS], gref) < 1e-4
+    assert _rel(out[ps.STREAM_SLABS], out[0]) < 1e-6
+
+
 def test_trispectrum_backward_limits(gpu):
     """More than 64 shells: the order-4 backward reports UNSUPPORTED (the plan is refused
     before any field is needed)."""
